@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Throughput of the FasterTucker hot path on one MI355X.
+
+A step is one iteration of Algorithm 2 on a Netflix-shaped synthetic tensor
+(480000 x 18000 x 2200, 100M distinct coordinates with per-mode Zipf(1.1)
+indices, integer values 1..5, J = R = 16, FP32): the factor pass of every
+mode and the core pass of every mode, each followed by its C refresh, then
+the RMSE pass.  The metric counts 2 N |Omega| element updates per step
+(one factor and one core visit per element and mode).
+
+Prints one JSON line.  The inputs are generated and uploaded before the
+timed region; the timed region holds only device work.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic(w, nnz, row_counts, chunk):
+    """Per-epoch algorithmic flops and bytes per kernel family (formulas in the design notes)."""
+    import numpy as np
+
+    N, J, R = len(w.dims), w.J[0], w.R
+    f_elem = 2 * J * R + (N - 2) * R + 5 * J
+    stream = (N - 1) * 4 + 4
+    out = {"factor_compose": [0.0, 0.0], "factor_apply": [0.0, 0.0], "segsum": [0.0, 0.0], "loss": [0.0, 0.0]}
+    c_bytes = [d * R * 4 for d in w.dims]
+    a_bytes = [d * J * 4 for d in w.dims]
+    for m in range(N):
+        L = row_counts[m]
+        heavy = L > chunk
+        comp = float(np.sum(np.where(heavy, L - chunk, 0)))
+        app = float(nnz - comp)
+        others = sum(c_bytes) - c_bytes[m]
+        out["factor_compose"][0] += comp * f_elem
+        out["factor_compose"][1] += comp * stream + others * comp / max(nnz, 1)
+        out["factor_apply"][0] += app * f_elem
+        out["factor_apply"][1] += app * stream + others * app / max(nnz, 1) + 2 * a_bytes[m]
+        out["segsum"][0] += nnz * ((N - 2) * R + 4 * R) + w.dims[m] * 2 * J * R
+        out["segsum"][1] += nnz * stream + others + c_bytes[m] + a_bytes[m]
+    out["loss"][0] += nnz * (N * R + 3)
+    out["loss"][1] += nnz * stream + sum(c_bytes)
+    return out
+
+
+def cpu_baseline(w, c, v, A, B, sample):
+    """The FP64 oracle, as it is, on the first `sample` elements of the same tensor (one thread)."""
+    import numpy as np
+
+    import oracle
+
+    cs = np.ascontiguousarray(c[:, :sample])
+    vs = v[:sample].astype(np.float64)
+    orc = oracle.Model(w.dims, w.J, w.R, cs, vs, [a.astype(np.float64) for a in A], [b.astype(np.float64) for b in B])
+    t = time.perf_counter()
+    orc.epoch(w.lr, w.lam, w.lr, w.lam)
+    orc.loss()
+    dt = time.perf_counter() - t
+    N = len(w.dims)
+    return {
+        "value": 2 * N * sample / dt,
+        "unit": "nnz-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"one epoch + RMSE of the FP64 C oracle on the first {sample} elements of the same tensor "
+        f"(same dims, J, R), {dt:.2f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="netflix")
+    ap.add_argument("--nnz", type=int, default=None, help="override the element count (smaller test runs)")
+    ap.add_argument("--cpu-sample", type=int, default=3_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(
+            json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md "
+                        "and not implemented", "n_gpus": args.gpus}),
+            flush=True,
+        )
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2210_06014_amd as ft
+    import synth
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}), flush=True)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]
+    nnz = w.nnz if args.nnz is None else args.nnz
+    N, J, R = len(w.dims), w.J[0], w.R
+
+    log(f"generating {args.workload}: dims={w.dims} nnz={nnz} zipf={w.zipf}")
+    t = time.time()
+    c, v, A, B = synth.make(w, nnz=nnz)
+    log(f"generated in {time.time() - t:.1f} s")
+    t = time.time()
+    plan = ft.Plan(w.dims, J, R, c, v)
+    log(f"plan built and uploaded in {time.time() - t:.1f} s ({plan.device_bytes() / 2**30:.2f} GiB on device)")
+    prm = ft.Params(A, B)
+    ft.refresh(plan, prm)
+    rmse0 = float(ft.loss(plan, prm)[1].item())
+    lossbuf = torch.empty(4, dtype=torch.float64, device="cuda")
+
+    for i in range(args.warmup):
+        ft.epoch(plan, prm, w.lr, w.lam, w.lr, w.lam)
+        ft.loss(plan, prm, out=lossbuf)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    if not args.no_profile:
+        plan.profile(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for i in range(args.steps):
+        ft.epoch(plan, prm, w.lr, w.lam, w.lr, w.lam)
+        ft.loss(plan, prm, out=lossbuf)
+    ev1.record()
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    prof = plan.profile_read() if not args.no_profile else {}
+    plan.profile(False)
+    ms_step = total_ms / args.steps
+    rmse = float(lossbuf[1].item())
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, RMSE {rmse0:.6f} -> {rmse:.6f}")
+
+    value = 2 * N * nnz / (ms_step / 1e3)
+    counts = [np.bincount(c[m], minlength=w.dims[m]) for m in range(N)]
+    alg = algorithmic(w, nnz, counts, 128)
+    kernels = {}
+    for k, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        kernels[k] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps, "avg_launch_us": 1e3 * ms / n}
+    roofline = None
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+        t_s = kernels[dom]["ms_per_step"] / 1e3
+        flops, byts = alg.get(dom, [0.0, 0.0])
+        if dom in ("factor_compose", "factor_apply"):
+            ach = flops / t_s / 1e12
+            roofline = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / PEAK_FP32_TFLOPS, "traffic": None}
+        else:
+            ach = byts / t_s / 1e9
+            roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": ach / PEAK_HBM_GBS, "traffic": None}
+        for k in kernels:
+            if k in alg:
+                t_k = kernels[k]["ms_per_step"] / 1e3
+                kernels[k]["alg_tflops"] = alg[k][0] / t_k / 1e12
+                kernels[k]["alg_gbs"] = alg[k][1] / t_k / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        s = min(args.cpu_sample, nnz)
+        log(f"CPU baseline: oracle on {s} elements")
+        cpu = cpu_baseline(w, c, v, A, B, s)
+        log(f"CPU baseline {cpu['value']:.3e} nnz-updates/s")
+
+    line = {
+        "metric": "SGD nnz updates/sec (factor+core)",
+        "value": value,
+        "unit": "nnz-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {'x'.join(map(str, w.dims))}, {nnz} distinct coordinates, "
+            f"Zipf({w.zipf}) per mode, values {w.value_kind}, J={J}, R={R}, lr={w.lr}, lam={w.lam}, init N(0,{w.sigma}^2)",
+            "step": "factor pass + C refresh per mode, core pass + C refresh per mode, RMSE pass",
+            "rmse_start": rmse0,
+            "rmse_end": rmse,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+/*
+ * fastertucker.h -- C-ABI of the MI355X (gfx950) FasterTucker hot path.
+ *
+ * Sparse FasterTucker (Li, Duan, Yang, Li; arXiv 2210.06014) approximates an
+ * N-order sparse tensor X on its observed set Omega by
+ *     xhat(i_1..i_N) = sum_r prod_n C(n)[i_n, r],   C(n) = A(n) B(n)
+ * (Eq. (1) evaluated through Eq. (12) and the reusable intermediate of
+ * Section 3.1), with factor matrices A(n) (I_n x J) and core matrices
+ * B(n) (J x R).  Training is Algorithm 2: per mode a factor pass (one SGD
+ * step per observed element on the row a(m)_{i_m}, Eq. (9)-(10)), then per
+ * mode a core pass (one step on B(m) with the gradient of Eq. (11) summed
+ * over Omega, Algorithm 5), each followed by a refresh of C(m).
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are dense row-major FP32 in device memory owned by the caller
+ *    (A(n): I_n x J, B(n): J x R, C(n): I_n x R).  All J_n must be equal.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *    Work is enqueued on it and the call returns without synchronising,
+ *    except where stated.  A plan may be shared by parameter sets; one plan
+ *    or parameter set must not be used on two streams at once (the plan owns
+ *    scratch buffers that every call reuses).
+ *  - Return value: FT_OK, or an error code with a message available from
+ *    ft_last_error() (thread-local).  Argument, shape and index errors are
+ *    detected on the host before anything is enqueued; FT_ERR_HIP reports a
+ *    failed HIP call or kernel launch.  No exception crosses the ABI.
+ *  - Floating point: FP32 arithmetic with FMA contraction, IEEE round to
+ *    nearest even.  Sums over elements run in a fixed order, so results are
+ *    bitwise repeatable for a given plan and input.  FP64 is used on the GPU
+ *    only for the loss reduction and for powers of the weight-decay factor.
+ */
+#ifndef FASTERTUCKER_H
+#define FASTERTUCKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FT_OK = 0,
+  FT_ERR_ARG = 1,         /* null pointer, negative size, bad mode number */
+  FT_ERR_SHAPE = 2,       /* order, dims, J, R or nnz out of range */
+  FT_ERR_INDEX = 3,       /* a coordinate outside its dimension */
+  FT_ERR_UNSUPPORTED = 4, /* (order, J, R) combination not compiled in */
+  FT_ERR_STATE = 5,       /* plan not uploaded, host copy not kept, ... */
+  FT_ERR_NOMEM = 6,       /* host allocation failed */
+  FT_ERR_HIP = 7          /* a HIP call failed (device memory, launch) */
+} ft_status;
+
+#define FT_MAX_ORDER 10
+
+/* ft_desc.flags */
+#define FT_KEEP_HOST 1 /* keep the host copy of the plan after upload (ft_plan_host_csr) */
+#define FT_WITH_PERM 2 /* keep element permutations on the device (ft_forward, ft_grad with upstream) */
+
+/* Shape of the problem and of the plan. */
+typedef struct {
+  int32_t order;                /* N, 2..FT_MAX_ORDER */
+  int64_t dims[FT_MAX_ORDER];   /* I_n, 1..2^31-1 */
+  int32_t J[FT_MAX_ORDER];      /* factor rank per mode; must all be equal */
+  int32_t R;                    /* core rank */
+  int64_t nnz;                  /* |Omega|, 0..2^32-1 */
+  int32_t chunk;                /* rows with more elements are split into chunks of this many (0: 128) */
+  int32_t fanin;                /* chunk maps folded per combine step (0: 64) */
+  int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM */
+} ft_desc;
+
+/* Device parameters of one model.  A[n], B[n], C[n] for n < order. */
+typedef struct {
+  float* A[FT_MAX_ORDER];
+  float* B[FT_MAX_ORDER];
+  float* C[FT_MAX_ORDER];
+} ft_params;
+
+/* Host-side statistics of one mode of a plan (for diagnostics and tests). */
+typedef struct {
+  int64_t rows;          /* I_m */
+  int64_t nonempty_rows; /* rows with at least one element */
+  int64_t max_row;       /* largest row length */
+  int64_t light_rows;    /* rows of at most `chunk` elements, updated in one piece */
+  int64_t heavy_rows;    /* longer rows, split into chunks */
+  int64_t chunks;        /* chunks of heavy rows, first chunks included */
+  int64_t segments;      /* pieces of rows used by the core, loss and gradient passes */
+  int32_t combine_levels;
+} ft_mode_info;
+
+typedef struct ft_plan ft_plan;
+
+/*
+ * ft_plan_create -- host-side plan (no GPU work).
+ *   coords: host int32, structure of arrays, coords[n * nnz + x] is the
+ *           mode-n index of element x (0-based).  vals: host float[nnz].
+ * For every mode m the elements are ordered by row i_m and, within a row,
+ * by the other indices taken cyclically (i_{m+1}, ..., i_{m-1}).  This is
+ * the order in which the factor pass visits a row's elements: the per-row
+ * order that the fiber-major walk of Algorithm 2 produces (Section 4.5
+ * describes the fiber tree whose leaves are the updated mode).
+ * Errors: FT_ERR_ARG, FT_ERR_SHAPE, FT_ERR_INDEX (any coordinate out of
+ * range), FT_ERR_UNSUPPORTED, FT_ERR_NOMEM.  The inputs are not retained.
+ */
+ft_status ft_plan_create(ft_plan** out, const ft_desc* desc, const int32_t* coords, const float* vals);
+
+/* ft_plan_upload -- allocates the plan's device memory and copies it
+ * (synchronous).  Frees the host copy unless FT_KEEP_HOST was given. */
+ft_status ft_plan_upload(ft_plan* plan, void* stream);
+
+/* Frees host and device memory of the plan (synchronises the device). */
+void ft_plan_destroy(ft_plan* plan);
+
+ft_status ft_plan_mode_info(const ft_plan* plan, int32_t mode, ft_mode_info* info);
+
+/* Device bytes held by the plan (valid after upload). */
+ft_status ft_plan_device_bytes(const ft_plan* plan, size_t* bytes);
+
+/*
+ * ft_plan_host_csr -- copy of the host CSR of one mode (needs FT_KEEP_HOST).
+ *   row_ptr int64[I_m + 1]; idx int32[(N-1) * nnz] where column k holds the
+ *   indices of mode (m + 1 + k) mod N; vals float[nnz]; perm int64[nnz]
+ *   maps a CSR position to the element's input position.  Any may be NULL.
+ */
+ft_status ft_plan_host_csr(const ft_plan* plan, int32_t mode, int64_t* row_ptr, int32_t* idx, float* vals,
+                           int64_t* perm);
+
+/*
+ * ft_refresh -- C(n) = A(n) B(n) for n = mode, or for every mode if mode < 0
+ * (the reusable intermediate of Section 3.1; Algorithm 3).  MFMA FP32.
+ */
+ft_status ft_refresh(const ft_plan* plan, const ft_params* p, int32_t mode, void* stream);
+
+/*
+ * ft_predict -- xhat for q query coordinates (device int32, structure of
+ * arrays [N][q]) into d_out float[q]: prediction of missing elements once A
+ * and B are found (Section 2.4).  Uses the C(n) in p, which must be current.
+ * Indices are not checked on the device; they must be in range.
+ */
+ft_status ft_predict(const ft_plan* plan, const ft_params* p, const int32_t* d_coords, int64_t q, float* d_out,
+                     void* stream);
+
+/*
+ * ft_factor_pass -- factor module of Algorithm 2 for one mode m: for every
+ * element x of Omega, in the plan's per-row order, with
+ *     w_x = prod_{n != m} C(n)[i_n, :]   (Eq. (12)),   g_x = B(m) w_x,
+ *     e = x - a.g_x,   a <- a + lr (e g_x - lam a)     (Eq. (9), (10))
+ * on a = A(m)[i_m, :].  Rows are independent within the pass; rows longer
+ * than the chunk length are split and the exact sequential result is
+ * recovered by composing the affine maps of the chunks.  C(m) is NOT
+ * refreshed (call ft_refresh, or use ft_factor_epoch).
+ */
+ft_status ft_factor_pass(const ft_plan* plan, const ft_params* p, int32_t mode, double lr, double lam,
+                         void* stream);
+
+/* ft_factor_epoch -- ft_factor_pass then ft_refresh for m = 0..N-1. */
+ft_status ft_factor_epoch(const ft_plan* plan, const ft_params* p, double lr, double lam, void* stream);
+
+/*
+ * ft_core_grad -- G = sum_{x in Omega} e_x A(m)[i_m, :]^T w_x  (J x R, FP32,
+ * row-major into d_G) at the current parameters: the accumulated gradient of
+ * Algorithm 5 (Eq. (11) without the regulariser, negated).
+ */
+ft_status ft_core_grad(const ft_plan* plan, const ft_params* p, int32_t mode, float* d_G, void* stream);
+
+/*
+ * ft_core_pass -- core module for mode m: B(m) <- B(m) + lr (G / |Omega| -
+ * lam B(m)) with G as in ft_core_grad (Algorithm 5).  C(m) is not refreshed.
+ */
+ft_status ft_core_pass(const ft_plan* plan, const ft_params* p, int32_t mode, double lr, double lam,
+                       void* stream);
+
+/* ft_core_epoch -- ft_core_pass then ft_refresh for m = 0..N-1. */
+ft_status ft_core_epoch(const ft_plan* plan, const ft_params* p, double lr, double lam, void* stream);
+
+/* ft_epoch -- one iteration of Algorithm 2: ft_factor_epoch, ft_core_epoch.
+ * C must be current on entry and is current on return. */
+ft_status ft_epoch(const ft_plan* plan, const ft_params* p, double lr_a, double lam_a, double lr_b, double lam_b,
+                   void* stream);
+
+/*
+ * ft_loss -- the objective of Eq. (6) in four FP64 numbers written to device
+ * memory d_out4: [sum_x (x - xhat)^2, sqrt(that / |Omega|),
+ * lam_a sum_n ||A(n)||^2, lam_b sum_n ||B(n)||^2].  Uses the current C.
+ */
+ft_status ft_loss(const ft_plan* plan, const ft_params* p, double lam_a, double lam_b, double* d_out4,
+                  void* stream);
+
+/* ft_forward -- xhat of every element of the plan, in input order, into
+ * d_out float[nnz].  Needs FT_WITH_PERM. */
+ft_status ft_forward(const ft_plan* plan, const ft_params* p, float* d_out, void* stream);
+
+/*
+ * ft_grad -- gradient of a loss L at fixed parameters given dL/dxhat_x:
+ *     dA(n)[i] = sum_{x: i_n = i} delta_x B(n) w(n)_x,
+ *     dB(n)    = sum_x delta_x A(n)[i_n, :]^T w(n)_x          (Eq. (10), (11))
+ * d_upstream: float[nnz] in input order (needs FT_WITH_PERM), or NULL for
+ * delta_x = -(x - xhat_x), the gradient of 1/2 sum e^2.  d_gA[n] (I_n x J)
+ * and d_gB[n] (J x R) are overwritten.  Uses the current C.
+ */
+ft_status ft_grad(const ft_plan* plan, const ft_params* p, const float* d_upstream, float* const* d_gA,
+                  float* const* d_gB, void* stream);
+
+/*
+ * Kernel timing.  While enabled on a plan, every launch of the kernels
+ * listed in ft_kernel_id is bracketed by two hipEvents recorded on the
+ * call's stream.  ft_profile_read waits for the recorded events, returns the
+ * accumulated milliseconds and launch counts per kernel (arrays of
+ * FT_K_COUNT entries, either may be NULL) and clears them.  Enabling or
+ * disabling also clears them.  Not for use while another thread launches
+ * work with the same plan.
+ */
+typedef enum {
+  FT_K_FACTOR_COMPOSE = 0, /* chunk maps of long rows */
+  FT_K_FACTOR_APPLY = 1,   /* short rows and first chunks, applied in place */
+  FT_K_COMBINE = 2,        /* folds of chunk maps */
+  FT_K_REFRESH = 3,        /* C = A B */
+  FT_K_SEGSUM = 4,         /* core and gradient segment sums */
+  FT_K_REDUCE = 5,         /* partial-sum reduction and B step */
+  FT_K_LOSS = 6,           /* loss and forward gather */
+  FT_K_COUNT = 7
+} ft_kernel_id;
+ft_status ft_profile_enable(ft_plan* plan, int32_t enable);
+ft_status ft_profile_read(ft_plan* plan, double* ms, int64_t* launches);
+
+/* Name of a status code, and the message of the last error on this thread. */
+const char* ft_status_str(ft_status s);
+const char* ft_last_error(void);
+
+/* Whether (order, J, R) has compiled kernels. */
+int32_t ft_supported(int32_t order, int32_t J, int32_t R);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

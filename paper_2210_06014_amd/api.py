@@ -1,0 +1,225 @@
+"""Python names for the C-ABI calls (argument marshalling only).
+
+Every function takes a :class:`Plan` (the sorted sparse tensor, built once)
+and a :class:`Params` (device tensors A(n), B(n), C(n)) and enqueues its
+kernels on torch's current stream.  Nothing here computes on the host.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import FtDesc, FtModeInfo, FtParams, check, load
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def supported(order: int, J: int, R: int) -> bool:
+    return bool(load().ft_supported(order, J, R))
+
+
+class Plan:
+    """Per-mode sorted copies of one sparse tensor plus work lists (ft_plan_create / ft_plan_upload).
+
+    coords: int32 [order][nnz] (host), vals: float32 [nnz] (host)."""
+
+    def __init__(self, dims, J, R, coords, vals, chunk=0, fanin=0, keep_host=False, with_perm=False, upload=True):
+        lib = load()
+        coords = np.ascontiguousarray(coords, dtype=np.int32)
+        vals = np.ascontiguousarray(vals, dtype=np.float32)
+        order = len(dims)
+        if coords.ndim != 2 or coords.shape[0] != order or vals.shape != (coords.shape[1],):
+            raise ValueError("coords must be [order][nnz] and vals [nnz]")
+        Js = [int(J)] * order if np.isscalar(J) else [int(j) for j in J]
+        d = FtDesc()
+        d.order = order
+        for n in range(order):
+            d.dims[n] = int(dims[n])
+            d.J[n] = Js[n]
+        d.R = int(R)
+        d.nnz = int(coords.shape[1])
+        d.chunk = int(chunk)
+        d.fanin = int(fanin)
+        d.flags = (_lib.FT_KEEP_HOST if keep_host else 0) | (_lib.FT_WITH_PERM if with_perm else 0)
+        self.dims = [int(x) for x in dims]
+        self.order = order
+        self.J = Js[0]
+        self.R = int(R)
+        self.nnz = int(coords.shape[1])
+        self._lib = lib
+        self._h = ctypes.c_void_p()
+        check(lib.ft_plan_create(ctypes.byref(self._h), ctypes.byref(d), coords.ctypes.data, vals.ctypes.data))
+        if upload:
+            self.upload()
+
+    def upload(self):
+        check(self._lib.ft_plan_upload(self._h, _stream()))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def mode_info(self, m: int) -> dict:
+        info = FtModeInfo()
+        check(self._lib.ft_plan_mode_info(self._h, int(m), ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in FtModeInfo._fields_}
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        check(self._lib.ft_plan_device_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def host_csr(self, m: int):
+        """(row_ptr, idx [(N-1), nnz], vals, perm) of mode m (plan built with keep_host=True)."""
+        I = self.dims[m]
+        row_ptr = np.empty(I + 1, dtype=np.int64)
+        idx = np.empty((self.order - 1, self.nnz), dtype=np.int32)
+        vals = np.empty(self.nnz, dtype=np.float32)
+        perm = np.empty(self.nnz, dtype=np.int64)
+        check(self._lib.ft_plan_host_csr(self._h, int(m), row_ptr.ctypes.data, idx.ctypes.data, vals.ctypes.data,
+                                         perm.ctypes.data))
+        return row_ptr, idx, vals, perm
+
+    def profile(self, enable: bool = True):
+        """Start (or stop) per-kernel event timing on this plan; clears the counters."""
+        check(self._lib.ft_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel: (total ms, launches)} since the last read; waits for the recorded events."""
+        ms = np.zeros(len(_lib.KERNELS), dtype=np.float64)
+        cnt = np.zeros(len(_lib.KERNELS), dtype=np.int64)
+        check(self._lib.ft_profile_read(self._h, ms.ctypes.data, cnt.ctypes.data))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(_lib.KERNELS)}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            self._lib.ft_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Params:
+    """Device parameters: A(n) (I_n x J), B(n) (J x R), C(n) (I_n x R) as contiguous float32 CUDA tensors."""
+
+    def __init__(self, A, B, C=None, device="cuda"):
+        import torch
+
+        self.A = [torch.as_tensor(a, dtype=torch.float32).to(device).contiguous() for a in A]
+        self.B = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for b in B]
+        if C is None:
+            self.C = [torch.empty((a.shape[0], b.shape[1]), dtype=torch.float32, device=device)
+                      for a, b in zip(self.A, self.B)]
+        else:
+            self.C = list(C)
+        self._struct = None
+
+    @property
+    def struct(self) -> FtParams:
+        s = FtParams()
+        for n, (a, b, c) in enumerate(zip(self.A, self.B, self.C)):
+            for t in (a, b, c):
+                if not (t.is_cuda and t.dtype.is_floating_point and t.is_contiguous()):
+                    raise ValueError("parameters must be contiguous CUDA float32 tensors")
+            s.A[n] = a.data_ptr()
+            s.B[n] = b.data_ptr()
+            s.C[n] = c.data_ptr()
+        self._struct = s
+        return s
+
+    def clone(self) -> "Params":
+        return Params([a.clone() for a in self.A], [b.clone() for b in self.B], [c.clone() for c in self.C])
+
+
+def _p(params: Params):
+    return ctypes.byref(params.struct)
+
+
+def refresh(plan: Plan, params: Params, mode: int = -1):
+    check(plan._lib.ft_refresh(plan.handle, _p(params), int(mode), _stream()))
+
+
+def predict(plan: Plan, params: Params, coords):
+    """coords: int32 CUDA tensor [order][q] -> float32 CUDA tensor [q]."""
+    import torch
+
+    coords = coords.contiguous()
+    q = coords.shape[1]
+    out = torch.empty(q, dtype=torch.float32, device=coords.device)
+    check(plan._lib.ft_predict(plan.handle, _p(params), coords.data_ptr(), q, out.data_ptr(), _stream()))
+    return out
+
+
+def factor_pass(plan: Plan, params: Params, mode: int, lr: float, lam: float):
+    check(plan._lib.ft_factor_pass(plan.handle, _p(params), int(mode), float(lr), float(lam), _stream()))
+
+
+def factor_epoch(plan: Plan, params: Params, lr: float, lam: float):
+    check(plan._lib.ft_factor_epoch(plan.handle, _p(params), float(lr), float(lam), _stream()))
+
+
+def core_grad(plan: Plan, params: Params, mode: int):
+    import torch
+
+    G = torch.empty((plan.J, plan.R), dtype=torch.float32, device="cuda")
+    check(plan._lib.ft_core_grad(plan.handle, _p(params), int(mode), G.data_ptr(), _stream()))
+    return G
+
+
+def core_pass(plan: Plan, params: Params, mode: int, lr: float, lam: float):
+    check(plan._lib.ft_core_pass(plan.handle, _p(params), int(mode), float(lr), float(lam), _stream()))
+
+
+def core_epoch(plan: Plan, params: Params, lr: float, lam: float):
+    check(plan._lib.ft_core_epoch(plan.handle, _p(params), float(lr), float(lam), _stream()))
+
+
+def epoch(plan: Plan, params: Params, lr_a: float, lam_a: float, lr_b: float, lam_b: float):
+    check(plan._lib.ft_epoch(plan.handle, _p(params), float(lr_a), float(lam_a), float(lr_b), float(lam_b),
+                             _stream()))
+
+
+def loss(plan: Plan, params: Params, lam_a: float = 0.0, lam_b: float = 0.0, out=None):
+    """Device float64 tensor [SSE, RMSE, lam_a sum ||A||^2, lam_b sum ||B||^2]."""
+    import torch
+
+    if out is None:
+        out = torch.empty(4, dtype=torch.float64, device="cuda")
+    check(plan._lib.ft_loss(plan.handle, _p(params), float(lam_a), float(lam_b), out.data_ptr(), _stream()))
+    return out
+
+
+def forward(plan: Plan, params: Params, out=None):
+    """xhat of every element in input order (plan built with with_perm=True)."""
+    import torch
+
+    if out is None:
+        out = torch.empty(plan.nnz, dtype=torch.float32, device="cuda")
+    check(plan._lib.ft_forward(plan.handle, _p(params), out.data_ptr(), _stream()))
+    return out
+
+
+def grad(plan: Plan, params: Params, upstream=None):
+    """(dA list, dB list) for dL/dxhat = upstream (input order), or of 1/2 sum e^2 when upstream is None."""
+    import torch
+
+    gA = [torch.empty_like(a) for a in params.A]
+    gB = [torch.empty_like(b) for b in params.B]
+    arrA = (ctypes.c_void_p * len(gA))(*[t.data_ptr() for t in gA])
+    arrB = (ctypes.c_void_p * len(gB))(*[t.data_ptr() for t in gB])
+    up = None
+    if upstream is not None:
+        upstream = upstream.contiguous().to(torch.float32)
+        up = upstream.data_ptr()
+    check(plan._lib.ft_grad(plan.handle, _p(params), up, arrA, arrB, _stream()))
+    return gA, gB

@@ -1,0 +1,157 @@
+// Internal structures shared by the host plan, the kernels and the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fastertucker.h"
+
+namespace ft {
+
+// Factor-pass work item: a whole light row (kind LIGHT), the first chunk of
+// a heavy row (HEAD, result written to the row's head vector) or a later
+// chunk of a heavy row (COMPOSE, its affine map written to a map slot).
+enum : int32_t { ITEM_LIGHT = 0, ITEM_HEAD = 1, ITEM_COMPOSE = 2 };
+
+struct FItem {
+  int64_t start;  // first CSR position
+  int32_t len;    // elements (0 for padding)
+  int32_t row;    // row of the updated mode
+  int32_t slot;   // head-vector slot (HEAD) or map slot (COMPOSE)
+  int32_t kind;
+};
+static_assert(sizeof(FItem) == 24, "FItem layout");
+
+// One step of the combine reduction: fold `count` consecutive maps starting
+// at in_off (in order) into one; write it to out_off, or if out_off < 0
+// apply it to the head vector `heavy` and write row `row` of A(m).
+struct CItem {
+  int64_t in_off;
+  int64_t out_off;
+  int32_t count;
+  int32_t row;
+  int32_t heavy;
+  int32_t pad;
+};
+static_assert(sizeof(CItem) == 32, "CItem layout");
+
+// A piece of a row for the core, loss and gradient passes.
+struct Seg {
+  int64_t start;
+  int32_t len;
+  int32_t row;
+};
+static_assert(sizeof(Seg) == 16, "Seg layout");
+
+struct ModeHost {
+  std::vector<int64_t> row_ptr;   // I+1
+  std::vector<int32_t> idx;       // (N-1) * nnz
+  std::vector<float> val;         // nnz
+  std::vector<int64_t> perm;      // nnz: CSR position -> input position
+  std::vector<FItem> compose;     // COMPOSE items, padded to multiples of 4
+  std::vector<FItem> apply;       // HEAD then LIGHT items, padded to multiples of 4
+  std::vector<std::vector<CItem>> levels;
+  std::vector<Seg> segs;
+  std::vector<int64_t> seg_ptr;   // I+1: segments of row i are seg_ptr[i]..seg_ptr[i+1]-1
+};
+
+struct ModeDev {
+  int64_t* row_ptr = nullptr;
+  int32_t* idx = nullptr;
+  float* val = nullptr;
+  int32_t* perm = nullptr;  // device permutation (int32: nnz < 2^31 required with FT_WITH_PERM)
+  FItem* compose = nullptr;
+  FItem* apply = nullptr;
+  CItem* levels = nullptr;  // all levels back to back
+  Seg* segs = nullptr;
+  int64_t* seg_ptr = nullptr;
+};
+
+struct ModeMeta {
+  int64_t I = 0;
+  int64_t n_compose = 0;  // padded counts
+  int64_t n_apply = 0;
+  int64_t n_heavy = 0;
+  int64_t n_maps = 0;     // COMPOSE items (unpadded)
+  std::vector<int64_t> level_off;  // offset of each level in the device array
+  std::vector<int64_t> level_len;
+  int64_t n_level_out0 = 0;        // outputs of level 0 (ping-pong buffer size)
+  int64_t n_segs = 0;
+  ft_mode_info info{};
+};
+
+}  // namespace ft
+
+struct ft_prof_rec {
+  int kid;
+  hipEvent_t start, stop;
+};
+
+struct ft_plan {
+  ft_desc desc{};
+  int N = 0, J = 0, R = 0;
+  int64_t nnz = 0;
+  int chunk = 128, fanin = 64;
+  std::vector<ft::ModeMeta> meta;
+  std::vector<ft::ModeHost> host;
+  std::vector<ft::ModeDev> dev;
+  bool host_valid = false;
+  bool uploaded = false;
+  // scratch shared by all modes (sized for the largest)
+  float* maps = nullptr;       // map slots (level ping-pong region 0 and 1)
+  int64_t* map_cnt = nullptr;
+  int64_t maps_region1 = 0;    // slot offset of region 1
+  float* hvec = nullptr;       // heavy rows' head vectors
+  float* partials = nullptr;   // per-workgroup partial sums (core/grad)
+  double* dpartials = nullptr; // per-workgroup FP64 partial sums (loss)
+  float* tseg = nullptr;       // per-segment row sums (gradient)
+  float* gbuf = nullptr;       // J x R gradient buffer
+  size_t device_bytes = 0;
+  // kernel timing (ft_profile_enable); launches on a const plan append to it
+  mutable bool prof_on = false;
+  mutable std::vector<ft_prof_rec> prof;
+};
+
+namespace ft {
+void set_error(const std::string& msg);
+ft_status fail(ft_status s, const std::string& msg);
+
+// kernel launchers (ft_kernels.hip); return hipSuccess or the launch error
+constexpr int kPartials = 2048;  // max workgroups of the reduction kernels
+constexpr int kSegLen = 512;     // max elements per segment
+
+// Brackets one kernel launch with events when timing is enabled on the plan.
+struct KTimer {
+  const ft_plan* P;
+  int kid;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  KTimer(const ft_plan* P_, int kid_, hipStream_t s_) : P(P_), kid(kid_), s(s_) {
+    if (P && P->prof_on && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+  }
+  ~KTimer() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, s) == hipSuccess)
+      P->prof.push_back(ft_prof_rec{kid, a, b});
+    else
+      (void)hipEventDestroy(a);
+  }
+};
+
+hipError_t launch_refresh(const ft_plan* P, int n, const ft_params* p, hipStream_t s);
+hipError_t launch_factor(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s);
+hipError_t launch_core_grad(const ft_plan* P, int m, const ft_params* p, hipStream_t s);  // result in P->gbuf
+hipError_t launch_core_update(const ft_plan* P, int m, const ft_params* p, double lr, double lam, float* G_out,
+                              hipStream_t s);
+hipError_t launch_loss(const ft_plan* P, const ft_params* p, double lam_a, double lam_b, double* out4, hipStream_t s);
+hipError_t launch_predict(const ft_plan* P, const ft_params* p, const int32_t* coords, int64_t q, float* out,
+                          hipStream_t s);
+hipError_t launch_forward(const ft_plan* P, const ft_params* p, float* out, hipStream_t s);
+hipError_t launch_grad(const ft_plan* P, const ft_params* p, const float* upstream, float* const* gA,
+                       float* const* gB, hipStream_t s);
+bool supported(int N, int J, int R);
+}  // namespace ft

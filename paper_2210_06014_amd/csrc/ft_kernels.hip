@@ -1,0 +1,836 @@
+// HIP kernels of the FasterTucker hot path for CDNA4 (gfx950, wave64).
+//
+// Lane layouts:
+//  * factor pass: a 16-lane DPP row owns one work item; lane l holds element
+//    j = l (+16 e) of every J-vector (row of A(m), shared intermediate g, a
+//    column of a chunk map) and element r = l (+16 q) of w; values of other
+//    lanes are read with DPP row_newbcast, row sums with DPP butterflies;
+//  * core, loss, gradient passes: a segment of a row per wavefront, R/4 lanes
+//    per element, each lane gathering a 16-byte slice of every C(n) row;
+//  * C refresh: v_mfma_f32_16x16x4_f32 tiles of 16 rows.
+// No floating-point atomics: every reduction runs in a fixed order.
+#include <type_traits>
+
+#include "ft_internal.h"
+
+namespace ft {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ int dppi(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+}
+// value of lane L of this lane's 16-lane row (DPP row_newbcast, gfx90a+)
+template <int L>
+__device__ __forceinline__ float bcast16(float v) {
+  return dpp<0x150 + L>(v);
+}
+template <int L>
+__device__ __forceinline__ int bcast16i(int v) {
+  return dppi<0x150 + L>(v);
+}
+// Sum over aligned groups of G lanes (G = 1, 2, 4, 8, 16); every lane of the
+// group ends with the same bits (each step adds two equal partial sums).
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+  if constexpr (G >= 2) v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  if constexpr (G >= 4) v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) v += dpp<0x141>(v);  // row_half_mirror
+  if constexpr (G >= 16) v += dpp<0x140>(v); // row_mirror
+  return v;
+}
+
+template <int N>
+struct CPtrs {
+  const float* p[N > 1 ? N - 1 : 1];
+};
+
+// ---------------------------------------------------------------------------
+// C = A B  (I x J) (J x R), FP32 MFMA 16x16x4.  One wavefront per 16 rows.
+// Operand layout of v_mfma_f32_16x16x4_f32: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; result register v of lane l is D[4*(l/16)+v][l%16].
+template <int J, int R>
+__global__ __launch_bounds__(256) void k_refresh(const float* __restrict__ A, const float* __restrict__ B,
+                                                 float* __restrict__ C, int64_t I) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (row0 >= I) return;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t ia = row0 + li;
+  constexpr int CT = (R + 15) / 16;
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int col = ct * 16 + li;
+#pragma unroll
+    for (int kb = 0; kb < J / 4; ++kb) {
+      const int k = kb * 4 + lk;
+      const float a = ia < I ? A[ia * J + k] : 0.f;
+      const float b = col < R ? B[k * R + col] : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = row0 + lk * 4 + v;
+      if (r < I && col < R) C[r * R + col] = acc[v];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Factor pass.  Each element x of a row, in order:
+//     w = prod_{n != m} C(n)[i_n, :],  g = B(m) w,  e = x - a.g,
+//     a <- a + (-lr lam) a + (lr e) g                       (Eq. (9), (10))
+// The decay is applied as an increment so that its rounding does not build
+// up over long rows.
+//
+// Per batch of 16 elements the lanes of a row first gather the C rows of all
+// 16 elements (phase 1, latency overlapped), then run the 16 dependent steps.
+// Steps past the end of an item use w = 0 and no decay, which leaves every
+// state unchanged, so the wavefront needs no divergent control flow.
+
+template <int N, int R>
+__device__ __forceinline__ void gather_w(const CPtrs<N>& cp, const int (&ix)[N > 1 ? N - 1 : 1], int l, int t0,
+                                         int len, float (&w)[16][R >= 16 ? R / 16 : 1]) {
+  constexpr int RE = R >= 16 ? R / 16 : 1;
+  static_for<0, 16>([&](auto S) {
+    constexpr int s = decltype(S)::value;
+    int ii[N - 1];
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) ii[k] = bcast16i<s>(ix[k]);
+    const bool sv = (t0 + s) < len;
+#pragma unroll
+    for (int q = 0; q < RE; ++q) {
+      const int r = R >= 16 ? l + 16 * q : (l % R);
+      float prod = cp.p[0][(int64_t)ii[0] * R + r];
+#pragma unroll
+      for (int k = 1; k < N - 1; ++k) prod *= cp.p[k][(int64_t)ii[k] * R + r];
+      w[s][q] = sv ? prod : 0.f;
+    }
+  });
+}
+
+template <int J, int R>
+__device__ __forceinline__ void shared_g(const float (&Bw)[J >= 16 ? J / 16 : 1][R], const float (&ws)[R >= 16 ? R / 16 : 1],
+                                         float (&g)[J >= 16 ? J / 16 : 1]) {
+  constexpr int E = J >= 16 ? J / 16 : 1;
+#pragma unroll
+  for (int e = 0; e < E; ++e) g[e] = 0.f;
+  static_for<0, R>([&](auto Rr) {
+    constexpr int r = decltype(Rr)::value;
+    const float wr = bcast16<r % 16>(ws[r / 16]);
+#pragma unroll
+    for (int e = 0; e < E; ++e) g[e] = fmaf(Bw[e][r], wr, g[e]);
+  });
+}
+
+template <int N, int J, int R>
+__global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ items, int64_t n_items,
+                                                      const int32_t* __restrict__ idx, int64_t nnz,
+                                                      const float* __restrict__ val, CPtrs<N> cp,
+                                                      const float* __restrict__ Bm, float* __restrict__ Am,
+                                                      float* __restrict__ hvec, float lr, float c1) {
+  constexpr int E = J >= 16 ? J / 16 : 1;
+  constexpr int RE = R >= 16 ? R / 16 : 1;
+  const int l = threadIdx.x & 15;
+  const int64_t gid = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  FItem it{0, 0, 0, 0, 0};
+  if (gid < n_items) it = items[gid];
+  float Bw[E][R];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = l + 16 * e;
+#pragma unroll
+    for (int r = 0; r < R; ++r) Bw[e][r] = j < J ? Bm[j * R + r] : 0.f;
+  }
+  float a[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = l + 16 * e;
+    a[e] = (it.len > 0 && j < J) ? Am[(int64_t)it.row * J + j] : 0.f;
+  }
+  int maxlen = it.len;
+  maxlen = max(maxlen, __shfl_xor(maxlen, 16));
+  maxlen = max(maxlen, __shfl_xor(maxlen, 32));
+  for (int t0 = 0; t0 < maxlen; t0 += 16) {
+    const bool vld = (t0 + l) < it.len;
+    const int64_t p = it.start + t0 + l;
+    int ix[N - 1];
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) ix[k] = vld ? idx[(int64_t)k * nnz + p] : 0;
+    const float xv = vld ? val[p] : 0.f;
+    float w[16][RE];
+    gather_w<N, R>(cp, ix, l, t0, it.len, w);
+    static_for<0, 16>([&](auto S) {
+      constexpr int s = decltype(S)::value;
+      float g[E];
+      shared_g<J, R>(Bw, w[s], g);
+      float pr = 0.f;
+#pragma unroll
+      for (int e = 0; e < E; ++e) pr = fmaf(a[e], g[e], pr);
+      pr = group_sum<16>(pr);
+      const float es = bcast16<s>(xv) - pr;
+      const float dec = (t0 + s) < it.len ? c1 : 0.f;
+      const float le = lr * es;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        a[e] = fmaf(dec, a[e], a[e]);
+        a[e] = fmaf(le, g[e], a[e]);
+      }
+    });
+  }
+  if (it.len > 0) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = l + 16 * e;
+      if (j < J) {
+        if (it.kind == ITEM_LIGHT)
+          Am[(int64_t)it.row * J + j] = a[e];
+        else
+          hvec[(int64_t)it.slot * J + j] = a[e];
+      }
+    }
+  }
+}
+
+// Chunk maps.  With rho = 1 - lr lam and gp = lr / rho, one step is
+//     a <- rho (I - gp g g^T) a + lr x g.
+// A chunk of T steps is the affine map a -> rho^T (I + Nm) a + v with
+//     Nm <- Nm - gp g (g + Nm^T g)^T     (Nm = prod (I - gp g g^T) - I)
+//     v  <- v + (-lr lam) v + lr (x - v.g) g
+// (v is the state reached from a = 0).  Lane j keeps column j of Nm.
+template <int N, int J, int R>
+__global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict__ items, int64_t n_items,
+                                                        const int32_t* __restrict__ idx, int64_t nnz,
+                                                        const float* __restrict__ val, CPtrs<N> cp,
+                                                        const float* __restrict__ Bm, float* __restrict__ maps,
+                                                        int64_t* __restrict__ map_cnt, float lr, float c1, float gp) {
+  constexpr int E = J >= 16 ? J / 16 : 1;
+  constexpr int RE = R >= 16 ? R / 16 : 1;
+  constexpr int MS = J * J + J;
+  const int l = threadIdx.x & 15;
+  const int64_t gid = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  FItem it{0, 0, 0, 0, 0};
+  if (gid < n_items) it = items[gid];
+  float Bw[E][R];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = l + 16 * e;
+#pragma unroll
+    for (int r = 0; r < R; ++r) Bw[e][r] = j < J ? Bm[j * R + r] : 0.f;
+  }
+  float Nc[E][J];
+  float v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    v[e] = 0.f;
+#pragma unroll
+    for (int i = 0; i < J; ++i) Nc[e][i] = 0.f;
+  }
+  int maxlen = it.len;
+  maxlen = max(maxlen, __shfl_xor(maxlen, 16));
+  maxlen = max(maxlen, __shfl_xor(maxlen, 32));
+  for (int t0 = 0; t0 < maxlen; t0 += 16) {
+    const bool vld = (t0 + l) < it.len;
+    const int64_t p = it.start + t0 + l;
+    int ix[N - 1];
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) ix[k] = vld ? idx[(int64_t)k * nnz + p] : 0;
+    const float xv = vld ? val[p] : 0.f;
+    float w[16][RE];
+    gather_w<N, R>(cp, ix, l, t0, it.len, w);
+    static_for<0, 16>([&](auto S) {
+      constexpr int s = decltype(S)::value;
+      float g[E];
+      shared_g<J, R>(Bw, w[s], g);
+      float gb[J];
+      static_for<0, J>([&](auto Ii) {
+        constexpr int i = decltype(Ii)::value;
+        gb[i] = bcast16<i % 16>(g[i / 16]);
+      });
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        float h = g[e];
+#pragma unroll
+        for (int i = 0; i < J; ++i) h = fmaf(Nc[e][i], gb[i], h);
+        const float t = -gp * h;
+#pragma unroll
+        for (int i = 0; i < J; ++i) Nc[e][i] = fmaf(t, gb[i], Nc[e][i]);
+      }
+      float pr = 0.f;
+#pragma unroll
+      for (int e = 0; e < E; ++e) pr = fmaf(v[e], g[e], pr);
+      pr = group_sum<16>(pr);
+      const float es = bcast16<s>(xv) - pr;
+      const float dec = (t0 + s) < it.len ? c1 : 0.f;
+      const float le = lr * es;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        v[e] = fmaf(dec, v[e], v[e]);
+        v[e] = fmaf(le, g[e], v[e]);
+      }
+    });
+  }
+  if (it.len > 0) {
+    float* dst = maps + (int64_t)it.slot * MS;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = l + 16 * e;
+      if (j < J) {
+#pragma unroll
+        for (int i = 0; i < J; ++i) dst[j * J + i] = Nc[e][i];  // column-major
+        dst[J * J + j] = v[e];
+      }
+    }
+    if (l == 0) map_cnt[it.slot] = it.len;
+  }
+}
+
+// Fold `count` consecutive maps (earliest first) into one:
+//   (s2, N2, v2) o (s1, N1, v1) = (s1 s2, N1 + N2 + N2 N1, s2 (v1 + N2 v1) + v2),
+// where s = rho^count.  The last fold of a row applies the map to the row's
+// head vector (the state after its first chunk) and writes A(m).
+template <int J>
+__global__ __launch_bounds__(256) void k_combine(const CItem* __restrict__ items, float* __restrict__ maps,
+                                                 int64_t* __restrict__ map_cnt, const float* __restrict__ hvec,
+                                                 float* __restrict__ Am, double rho) {
+  constexpr int MS = J * J + J;
+  constexpr int PER = (J * J + 255) / 256;
+  __shared__ float accN[J * J], accV[J], curN[J * J], curV[J];
+  const CItem it = items[blockIdx.x];
+  const int t = threadIdx.x;
+  const float* src0 = maps + it.in_off * MS;
+  for (int k = t; k < MS; k += 256) {
+    const float x = src0[k];
+    if (k < J * J)
+      accN[k] = x;
+    else
+      accV[k - J * J] = x;
+  }
+  int64_t cnt = map_cnt[it.in_off];
+  __syncthreads();
+  for (int c = 1; c < it.count; ++c) {
+    const int64_t slot = it.in_off + c;
+    const float* src = maps + slot * MS;
+    for (int k = t; k < MS; k += 256) {
+      const float x = src[k];
+      if (k < J * J)
+        curN[k] = x;
+      else
+        curV[k - J * J] = x;
+    }
+    const int64_t ck = map_cnt[slot];
+    __syncthreads();
+    float nn[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + 256 * u;
+      if (e < J * J) {
+        const int i = e % J, j = e / J;
+        float s = 0.f;
+#pragma unroll
+        for (int q = 0; q < J; ++q) s = fmaf(curN[q * J + i], accN[j * J + q], s);
+        nn[u] = (accN[e] + curN[e]) + s;
+      }
+    }
+    float vv = 0.f;
+    if (t < J) {
+      float s = 0.f;
+#pragma unroll
+      for (int q = 0; q < J; ++q) s = fmaf(curN[q * J + t], accV[q], s);
+      const double sk = pow(rho, (double)ck);
+      vv = (float)(sk * ((double)accV[t] + (double)s)) + curV[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + 256 * u;
+      if (e < J * J) accN[e] = nn[u];
+    }
+    if (t < J) accV[t] = vv;
+    cnt += ck;
+    __syncthreads();
+  }
+  if (it.out_off >= 0) {
+    float* dst = maps + it.out_off * MS;
+    for (int k = t; k < MS; k += 256) dst[k] = k < J * J ? accN[k] : accV[k - J * J];
+    if (t == 0) map_cnt[it.out_off] = cnt;
+  } else if (t < J) {
+    const float* a0 = hvec + (int64_t)it.heavy * J;
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < J; ++q) s = fmaf(accN[q * J + t], a0[q], s);
+    const double sc = pow(rho, (double)cnt);
+    Am[(int64_t)it.row * J + t] = (float)(sc * ((double)a0[t] + (double)s)) + accV[t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Segment passes (core gradient, loss, forward, gradient).  A wavefront takes
+// segments gw, gw + nw, ... (a fixed assignment), R/4 lanes per element.
+
+template <int N, int R>
+__device__ __forceinline__ floatx4 gather_w4(const CPtrs<N>& cp, const int32_t* __restrict__ idx, int64_t nnz,
+                                             int64_t p, bool vld, int q) {
+  floatx4 w = {1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+  for (int k = 0; k < N - 1; ++k) {
+    const int32_t ik = vld ? idx[(int64_t)k * nnz + p] : 0;
+    const floatx4 c = *reinterpret_cast<const floatx4*>(cp.p[k] + (int64_t)ik * R + 4 * q);
+    w *= c;
+  }
+  return w;
+}
+
+// MODE 0: s = sum e w (core gradient); MODE 1: t = sum -e w (gradient of 1/2 sum e^2);
+// MODE 2: t = sum delta w with delta from the caller (input order, via perm).
+template <int N, int J, int R, int MODE>
+__global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, int64_t nseg,
+                                                const int32_t* __restrict__ idx, int64_t nnz,
+                                                const float* __restrict__ val, CPtrs<N> cp,
+                                                const float* __restrict__ Cm, const float* __restrict__ Am,
+                                                const float* __restrict__ up, const int32_t* __restrict__ perm,
+                                                float* __restrict__ partials, float* __restrict__ tseg) {
+  constexpr int QL = R / 4;
+  constexpr int P = 64 / QL;
+  constexpr int GJ = (J + P - 1) / P;
+  __shared__ float red[4][J * R];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int slot = lane / QL, q = lane % QL;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  float Gp[GJ][4];
+#pragma unroll
+  for (int u = 0; u < GJ; ++u)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Gp[u][c] = 0.f;
+  for (int64_t sg = (int64_t)blockIdx.x * 4 + wave; sg < nseg; sg += nw) {
+    const Seg S = segs[sg];
+    floatx4 crow = {0.f, 0.f, 0.f, 0.f};
+    if (MODE != 2) crow = *reinterpret_cast<const floatx4*>(Cm + (int64_t)S.row * R + 4 * q);
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int t0 = 0; t0 < S.len; t0 += P) {
+      const bool vld = (t0 + slot) < S.len;
+      const int64_t p = S.start + t0 + slot;
+      const floatx4 w = gather_w4<N, R>(cp, idx, nnz, p, vld, q);
+      float d;
+      if (MODE == 2) {
+        d = vld ? up[perm[p]] : 0.f;
+      } else {
+        float xh = crow[0] * w[0];
+        xh = fmaf(crow[1], w[1], xh);
+        xh = fmaf(crow[2], w[2], xh);
+        xh = fmaf(crow[3], w[3], xh);
+        xh = group_sum<QL>(xh);
+        const float x = vld ? val[p] : 0.f;
+        d = vld ? (MODE == 0 ? x - xh : xh - x) : 0.f;
+      }
+      acc[0] = fmaf(d, w[0], acc[0]);
+      acc[1] = fmaf(d, w[1], acc[1]);
+      acc[2] = fmaf(d, w[2], acc[2]);
+      acc[3] = fmaf(d, w[3], acc[3]);
+    }
+#pragma unroll
+    for (int off = QL; off < 64; off <<= 1)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] += __shfl_xor(acc[c], off);
+    if (tseg && slot == 0) *reinterpret_cast<floatx4*>(tseg + sg * R + 4 * q) = acc;
+#pragma unroll
+    for (int u = 0; u < GJ; ++u) {
+      const int j = slot + P * u;
+      if (j < J) {
+        const float aj = Am[(int64_t)S.row * J + j];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Gp[u][c] = fmaf(aj, acc[c], Gp[u][c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < GJ; ++u) {
+    const int j = slot + P * u;
+    if (j < J)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) red[wave][j * R + 4 * q + c] = Gp[u][c];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < J * R; e += 256)
+    partials[(int64_t)blockIdx.x * J * R + e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+}
+
+// Sum of the workgroup partials in a fixed order; optionally the core step
+// B <- B + lr (G / |Omega| - lam B) (Algorithm 5).
+__global__ __launch_bounds__(256) void k_reduce_update(const float* __restrict__ partials, int nparts, int JR,
+                                                       float* __restrict__ Bm, float* __restrict__ Gout, float lr,
+                                                       float lam, float inv_nnz, int update) {
+  for (int e = threadIdx.x; e < JR; e += blockDim.x) {
+    float s = 0.f;
+    for (int b = 0; b < nparts; ++b) s += partials[(int64_t)b * JR + e];
+    if (Gout) Gout[e] = s;
+    if (update) {
+      const float b = Bm[e];
+      Bm[e] = b + lr * (s * inv_nnz - lam * b);
+    }
+  }
+}
+
+// dA(m)[i, j] = sum_r B(m)[j, r] t_i[r], t_i = sum of the row's segment sums.
+template <int J, int R>
+__global__ __launch_bounds__(256) void k_grad_rows(const int64_t* __restrict__ seg_ptr, const float* __restrict__ tseg,
+                                                   const float* __restrict__ Bm, float* __restrict__ gA, int64_t I) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= I * J) return;
+  const int64_t i = e / J;
+  const int j = (int)(e % J);
+  float t[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) t[r] = 0.f;
+  for (int64_t sg = seg_ptr[i]; sg < seg_ptr[i + 1]; ++sg)
+#pragma unroll
+    for (int r = 0; r < R; ++r) t[r] += tseg[sg * R + r];
+  float s = 0.f;
+#pragma unroll
+  for (int r = 0; r < R; ++r) s = fmaf(Bm[j * R + r], t[r], s);
+  gA[e] = s;
+}
+
+// Loss: per-element e^2 summed in FP64 (and, with out != nullptr, xhat stored
+// at the element's input position).
+template <int N, int R>
+__global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int64_t nseg,
+                                              const int32_t* __restrict__ idx, int64_t nnz,
+                                              const float* __restrict__ val, CPtrs<N> cp,
+                                              const float* __restrict__ Cm, double* __restrict__ dpart,
+                                              const int32_t* __restrict__ perm, float* __restrict__ out) {
+  constexpr int QL = R / 4;
+  constexpr int P = 64 / QL;
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int slot = lane / QL, q = lane % QL;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  double sse = 0.0;
+  for (int64_t sg = (int64_t)blockIdx.x * 4 + wave; sg < nseg; sg += nw) {
+    const Seg S = segs[sg];
+    const floatx4 crow = *reinterpret_cast<const floatx4*>(Cm + (int64_t)S.row * R + 4 * q);
+    for (int t0 = 0; t0 < S.len; t0 += P) {
+      const bool vld = (t0 + slot) < S.len;
+      const int64_t p = S.start + t0 + slot;
+      const floatx4 w = gather_w4<N, R>(cp, idx, nnz, p, vld, q);
+      float xh = crow[0] * w[0];
+      xh = fmaf(crow[1], w[1], xh);
+      xh = fmaf(crow[2], w[2], xh);
+      xh = fmaf(crow[3], w[3], xh);
+      xh = group_sum<QL>(xh);
+      if (vld && q == 0) {
+        const float e = val[p] - xh;
+        sse += (double)e * (double)e;
+        if (out) out[perm[p]] = xh;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) sse += __shfl_xor(sse, off);
+  if (lane == 0) red[wave] = sse;
+  __syncthreads();
+  if (threadIdx.x == 0 && dpart) dpart[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// FP64 sum of squares of a matrix, one partial per workgroup.
+__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ X, int64_t n, double* __restrict__ dpart) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+    const double x = X[k];
+    s += x * x;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dpart[blockIdx.x] = red[0];
+}
+
+constexpr int kSumsqBlocks = 32;
+
+__global__ void k_loss_finish(const double* __restrict__ dpart, int n_sse, const double* __restrict__ rpart,
+                              int n_a, int n_b, double nnz, double lam_a, double lam_b, double* __restrict__ out4) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double sse = 0.0, ra = 0.0, rb = 0.0;
+  for (int k = 0; k < n_sse; ++k) sse += dpart[k];
+  for (int k = 0; k < n_a; ++k) ra += rpart[k];
+  for (int k = 0; k < n_b; ++k) rb += rpart[n_a + k];
+  out4[0] = sse;
+  out4[1] = nnz > 0 ? sqrt(sse / nnz) : 0.0;
+  out4[2] = lam_a * ra;
+  out4[3] = lam_b * rb;
+}
+
+// Predictions for query coordinates (structure of arrays [N][q]).
+template <int N, int R>
+__global__ __launch_bounds__(256) void k_predict(const int32_t* __restrict__ coords, int64_t q,
+                                                 CPtrs<N + 1> cp, float* __restrict__ out) {
+  constexpr int QL = R / 4;
+  const int64_t tid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t x = tid / QL;
+  const int qq = (int)(tid % QL);
+  const bool vld = x < q;
+  floatx4 w = {1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    const int32_t i = vld ? coords[(int64_t)n * q + x] : 0;
+    const floatx4 c = *reinterpret_cast<const floatx4*>(cp.p[n] + (int64_t)i * R + 4 * qq);
+    w *= c;
+  }
+  float s = ((w[0] + w[1]) + w[2]) + w[3];
+  s = group_sum<QL>(s);
+  if (vld && qq == 0) out[x] = s;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+
+#define FT_CONFIGS(X) X(3, 8, 8) X(3, 16, 16) X(3, 32, 32) X(4, 8, 8) X(4, 32, 32) X(8, 8, 16)
+
+constexpr int key(int N, int J, int R) { return (N * 64 + J) * 64 + R; }
+
+template <int N>
+CPtrs<N> others(const ft_params* p, int m) {
+  CPtrs<N> c{};
+  for (int k = 0; k < N - 1; ++k) c.p[k] = p->C[(m + 1 + k) % N];
+  return c;
+}
+
+template <int N, int J, int R>
+hipError_t factor_impl(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
+  const ModeMeta& M = P->meta[m];
+  const ModeDev& D = P->dev[m];
+  const CPtrs<N> cp = others<N>(p, m);
+  const double rho = 1.0 - lr * lam;
+  const float flr = (float)lr, c1 = (float)(-lr * lam), gp = (float)(lr / rho);
+  if (M.n_compose > 0) {
+    KTimer tm(P, FT_K_FACTOR_COMPOSE, s);
+    hipLaunchKernelGGL((k_factor_compose<N, J, R>), dim3((unsigned)((M.n_compose + 15) / 16)), dim3(256), 0, s,
+                       D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, p->B[m], P->maps, P->map_cnt, flr, c1, gp);
+  }
+  if (M.n_apply > 0) {
+    KTimer tm(P, FT_K_FACTOR_APPLY, s);
+    hipLaunchKernelGGL((k_factor_apply<N, J, R>), dim3((unsigned)((M.n_apply + 15) / 16)), dim3(256), 0, s, D.apply,
+                       M.n_apply, D.idx, P->nnz, D.val, cp, p->B[m], p->A[m], P->hvec, flr, c1);
+  }
+  for (size_t L = 0; L < M.level_len.size(); ++L) {
+    KTimer tm(P, FT_K_COMBINE, s);
+    hipLaunchKernelGGL((k_combine<J>), dim3((unsigned)M.level_len[L]), dim3(256), 0, s, D.levels + M.level_off[L],
+                       P->maps, P->map_cnt, P->hvec, p->A[m], rho);
+  }
+  return hipGetLastError();
+}
+
+int seg_blocks(int64_t nseg) {
+  int64_t b = (nseg + 3) / 4;
+  if (b > kPartials) b = kPartials;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <int N, int J, int R>
+hipError_t segsum_impl(const ft_plan* P, int m, const ft_params* p, int mode, const float* up, float* tseg,
+                       hipStream_t s, int* nblocks) {
+  const ModeMeta& M = P->meta[m];
+  const ModeDev& D = P->dev[m];
+  const CPtrs<N> cp = others<N>(p, m);
+  const int nb = seg_blocks(M.n_segs);
+  *nblocks = nb;
+  KTimer tm(P, FT_K_SEGSUM, s);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_segsum<N, J, R, 0>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp,
+                       p->C[m], p->A[m], nullptr, nullptr, P->partials, tseg);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_segsum<N, J, R, 1>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp,
+                       p->C[m], p->A[m], nullptr, nullptr, P->partials, tseg);
+  else
+    hipLaunchKernelGGL((k_segsum<N, J, R, 2>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp,
+                       p->C[m], p->A[m], up, D.perm, P->partials, tseg);
+  return hipGetLastError();
+}
+
+template <int N, int J, int R>
+hipError_t loss_impl(const ft_plan* P, const ft_params* p, double lam_a, double lam_b, double* out4, float* xout,
+                     hipStream_t s) {
+  const ModeMeta& M = P->meta[0];
+  const ModeDev& D = P->dev[0];
+  const CPtrs<N> cp = others<N>(p, 0);
+  const int nb = seg_blocks(M.n_segs);
+  KTimer tm(P, FT_K_LOSS, s);
+  hipLaunchKernelGGL((k_loss<N, R>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp, p->C[0],
+                     out4 ? P->dpartials : nullptr, D.perm, xout);
+  if (!out4) return hipGetLastError();
+  double* rpart = P->dpartials + kPartials;
+  for (int n = 0; n < N; ++n)
+    hipLaunchKernelGGL(k_sumsq, dim3(kSumsqBlocks), dim3(256), 0, s, p->A[n], P->desc.dims[n] * J,
+                       rpart + n * kSumsqBlocks);
+  for (int n = 0; n < N; ++n)
+    hipLaunchKernelGGL(k_sumsq, dim3(kSumsqBlocks), dim3(256), 0, s, p->B[n], (int64_t)J * R,
+                       rpart + (N + n) * kSumsqBlocks);
+  hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(64), 0, s, P->dpartials, nb, rpart, N * kSumsqBlocks,
+                     N * kSumsqBlocks, (double)P->nnz, lam_a, lam_b, out4);
+  return hipGetLastError();
+}
+
+template <int N, int R>
+hipError_t predict_impl(const ft_params* p, const int32_t* coords, int64_t q, float* out, hipStream_t s) {
+  CPtrs<N + 1> cp{};
+  for (int n = 0; n < N; ++n) cp.p[n] = p->C[n];
+  const int64_t threads = q * (R / 4);
+  const unsigned nb = (unsigned)((threads + 255) / 256);
+  if (nb > 0) hipLaunchKernelGGL((k_predict<N, R>), dim3(nb), dim3(256), 0, s, coords, q, cp, out);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool supported(int N, int J, int R) {
+  switch (key(N, J, R)) {
+#define X(n, j, r) \
+  case key(n, j, r): return true;
+    FT_CONFIGS(X)
+#undef X
+    default: return false;
+  }
+}
+
+hipError_t launch_refresh(const ft_plan* P, int n, const ft_params* p, hipStream_t s) {
+  const int64_t I = P->desc.dims[n];
+  const float* A = p->A[n];
+  const float* B = p->B[n];
+  float* C = p->C[n];
+  const unsigned nb = (unsigned)(((I + 15) / 16 + 3) / 4);
+  if (nb == 0) return hipSuccess;
+  KTimer tm(P, FT_K_REFRESH, s);
+  switch (P->J * 64 + P->R) {
+#define X(n, j, r)                                                                              \
+  case j * 64 + r:                                                                              \
+    hipLaunchKernelGGL((k_refresh<j, r>), dim3(nb), dim3(256), 0, s, A, B, C, I);               \
+    return hipGetLastError();
+    X(0, 8, 8) X(0, 16, 16) X(0, 32, 32) X(0, 8, 16)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_factor(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
+  switch (key(P->N, P->J, P->R)) {
+#define X(n, j, r) \
+  case key(n, j, r): return factor_impl<n, j, r>(P, m, p, lr, lam, s);
+    FT_CONFIGS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static hipError_t segsum(const ft_plan* P, int m, const ft_params* p, int mode, const float* up, float* tseg,
+                         hipStream_t s, int* nb) {
+  switch (key(P->N, P->J, P->R)) {
+#define X(n, j, r) \
+  case key(n, j, r): return segsum_impl<n, j, r>(P, m, p, mode, up, tseg, s, nb);
+    FT_CONFIGS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_core_grad(const ft_plan* P, int m, const ft_params* p, hipStream_t s) {
+  int nb = 0;
+  hipError_t e = segsum(P, m, p, 0, nullptr, nullptr, s, &nb);
+  if (e != hipSuccess) return e;
+  {
+    KTimer tm(P, FT_K_REDUCE, s);
+    hipLaunchKernelGGL(k_reduce_update, dim3(1), dim3(256), 0, s, P->partials, nb, P->J * P->R, nullptr, P->gbuf,
+                       0.f, 0.f, 0.f, 0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_core_update(const ft_plan* P, int m, const ft_params* p, double lr, double lam, float* G_out,
+                              hipStream_t s) {
+  int nb = 0;
+  hipError_t e = segsum(P, m, p, 0, nullptr, nullptr, s, &nb);
+  if (e != hipSuccess) return e;
+  const float inv = P->nnz > 0 ? (float)(1.0 / (double)P->nnz) : 0.f;
+  KTimer tm(P, FT_K_REDUCE, s);
+  hipLaunchKernelGGL(k_reduce_update, dim3(1), dim3(256), 0, s, P->partials, nb, P->J * P->R, p->B[m], G_out,
+                     (float)lr, (float)lam, inv, P->nnz > 0 ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss(const ft_plan* P, const ft_params* p, double lam_a, double lam_b, double* out4, hipStream_t s) {
+  switch (key(P->N, P->J, P->R)) {
+#define X(n, j, r) \
+  case key(n, j, r): return loss_impl<n, j, r>(P, p, lam_a, lam_b, out4, nullptr, s);
+    FT_CONFIGS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_forward(const ft_plan* P, const ft_params* p, float* out, hipStream_t s) {
+  switch (key(P->N, P->J, P->R)) {
+#define X(n, j, r) \
+  case key(n, j, r): return loss_impl<n, j, r>(P, p, 0.0, 0.0, nullptr, out, s);
+    FT_CONFIGS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_predict(const ft_plan* P, const ft_params* p, const int32_t* coords, int64_t q, float* out,
+                          hipStream_t s) {
+  switch (key(P->N, P->J, P->R)) {
+#define X(n, j, r) \
+  case key(n, j, r): return predict_impl<n, r>(p, coords, q, out, s);
+    FT_CONFIGS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_grad(const ft_plan* P, const ft_params* p, const float* up, float* const* gA, float* const* gB,
+                       hipStream_t s) {
+  for (int m = 0; m < P->N; ++m) {
+    int nb = 0;
+    hipError_t e = segsum(P, m, p, up ? 2 : 1, up, P->tseg, s, &nb);
+    if (e != hipSuccess) return e;
+    const int64_t I = P->desc.dims[m];
+    const unsigned gb = (unsigned)((I * P->J + 255) / 256);
+    switch (P->J * 64 + P->R) {
+#define X(n, j, r)                                                                                               \
+  case j * 64 + r:                                                                                               \
+    hipLaunchKernelGGL((k_grad_rows<j, r>), dim3(gb), dim3(256), 0, s, P->dev[m].seg_ptr, P->tseg, p->B[m], gA[m], \
+                       I);                                                                                       \
+    break;
+      X(0, 8, 8) X(0, 16, 16) X(0, 32, 32) X(0, 8, 16)
+#undef X
+      default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_reduce_update, dim3(1), dim3(256), 0, s, P->partials, nb, P->J * P->R, nullptr, gB[m], 0.f,
+                       0.f, 0.f, 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace ft

@@ -1,0 +1,430 @@
+// Host side of a plan: validation, per-mode sort into CSR, work lists for the
+// factor, combine and segment kernels, and the upload to device memory.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <thread>
+
+#include "ft_internal.h"
+
+namespace ft {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+ft_status fail(ft_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+const char* last_error() { return g_last_error.c_str(); }
+
+static int num_threads() {
+  unsigned h = std::thread::hardware_concurrency();
+  if (h == 0) h = 1;
+  if (h > 32) h = 32;
+  return (int)h;
+}
+
+template <class F>
+static void parallel_for(int T, F f) {
+  if (T <= 1) {
+    f(0);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(T);
+  for (int t = 0; t < T; ++t) th.emplace_back(f, t);
+  for (auto& x : th) x.join();
+}
+
+static int bits_for(int64_t n) {
+  int b = 0;
+  while (((int64_t)1 << b) < n) ++b;
+  return b;
+}
+
+// Stable LSD radix sort of `order` (a permutation of 0..n-1) by key[order[j]].
+static void radix_by_column(const int32_t* key, int64_t dim, std::vector<uint32_t>& order,
+                            std::vector<uint32_t>& tmp, int T) {
+  const int64_t n = (int64_t)order.size();
+  int bits = bits_for(dim);
+  if (bits == 0) return;
+  int passes = (bits + 11) / 12;
+  int digit = (bits + passes - 1) / passes;
+  const int64_t B = (int64_t)1 << digit;
+  std::vector<int64_t> hist((size_t)T * B);
+  const int64_t per = (n + T - 1) / T;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = pass * digit;
+    const uint32_t mask = (uint32_t)(B - 1);
+    const uint32_t* src = order.data();
+    uint32_t* dst = tmp.data();
+    parallel_for(T, [&](int t) {
+      int64_t* h = hist.data() + (size_t)t * B;
+      std::fill(h, h + B, 0);
+      int64_t lo = t * per, hi = std::min(n, lo + per);
+      for (int64_t j = lo; j < hi; ++j) ++h[((uint32_t)key[src[j]] >> shift) & mask];
+    });
+    int64_t run = 0;
+    for (int64_t d = 0; d < B; ++d)
+      for (int t = 0; t < T; ++t) {
+        int64_t c = hist[(size_t)t * B + d];
+        hist[(size_t)t * B + d] = run;
+        run += c;
+      }
+    parallel_for(T, [&](int t) {
+      int64_t* h = hist.data() + (size_t)t * B;
+      int64_t lo = t * per, hi = std::min(n, lo + per);
+      for (int64_t j = lo; j < hi; ++j) {
+        uint32_t v = src[j];
+        dst[h[((uint32_t)key[v] >> shift) & mask]++] = v;
+      }
+    });
+    order.swap(tmp);
+  }
+}
+
+static void pad4(std::vector<FItem>& v, int32_t kind) {
+  while (v.size() % 4) v.push_back(FItem{0, 0, 0, 0, kind});
+}
+
+static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const float* vals, int T) {
+  const int N = P->N;
+  const int64_t nnz = P->nnz;
+  const int64_t I = P->desc.dims[m];
+  ModeHost& H = P->host[m];
+  ModeMeta& M = P->meta[m];
+  M.I = I;
+  try {
+    std::vector<uint32_t> order((size_t)nnz), tmp((size_t)nnz);
+    for (int64_t j = 0; j < nnz; ++j) order[j] = (uint32_t)j;
+    // least significant first: i_{m-1}, ..., i_{m+1}, then i_m
+    for (int k = N - 1; k >= 0; --k) {
+      int n = (m + k) % N;
+      radix_by_column(coords + (int64_t)n * nnz, P->desc.dims[n], order, tmp, T);
+    }
+    tmp.clear();
+    tmp.shrink_to_fit();
+    H.row_ptr.assign((size_t)I + 1, 0);
+    const int32_t* im = coords + (int64_t)m * nnz;
+    for (int64_t j = 0; j < nnz; ++j) ++H.row_ptr[(size_t)im[j] + 1];
+    for (int64_t i = 0; i < I; ++i) H.row_ptr[i + 1] += H.row_ptr[i];
+    H.idx.resize((size_t)(N - 1) * nnz);
+    H.val.resize((size_t)nnz);
+    H.perm.resize((size_t)nnz);
+    const int64_t per = (nnz + T - 1) / T;
+    parallel_for(T, [&](int t) {
+      int64_t lo = t * per, hi = std::min(nnz, lo + per);
+      for (int64_t p = lo; p < hi; ++p) {
+        uint32_t x = order[p];
+        for (int k = 1; k < N; ++k) H.idx[(size_t)(k - 1) * nnz + p] = coords[(int64_t)((m + k) % N) * nnz + x];
+        H.val[p] = vals[x];
+        H.perm[p] = x;
+      }
+    });
+  } catch (const std::bad_alloc&) {
+    return fail(FT_ERR_NOMEM, "host allocation failed while sorting mode " + std::to_string(m));
+  }
+
+  // factor work lists
+  const int64_t chunk = P->chunk;
+  std::vector<FItem> light, head;
+  int64_t n_heavy = 0, n_maps = 0, max_row = 0, nonempty = 0;
+  std::vector<int64_t> heavy_rows, heavy_base, heavy_nmaps;
+  for (int64_t i = 0; i < I; ++i) {
+    int64_t s = H.row_ptr[i], L = H.row_ptr[i + 1] - s;
+    if (L == 0) continue;
+    ++nonempty;
+    max_row = std::max(max_row, L);
+    if (L <= chunk) {
+      light.push_back(FItem{s, (int32_t)L, (int32_t)i, 0, ITEM_LIGHT});
+      continue;
+    }
+    int64_t K = (L + chunk - 1) / chunk;
+    head.push_back(FItem{s, (int32_t)chunk, (int32_t)i, (int32_t)n_heavy, ITEM_HEAD});
+    heavy_rows.push_back(i);
+    heavy_base.push_back(n_maps);
+    heavy_nmaps.push_back(K - 1);
+    for (int64_t c = 1; c < K; ++c) {
+      int64_t st = s + c * chunk;
+      H.compose.push_back(
+          FItem{st, (int32_t)std::min(chunk, L - c * chunk), (int32_t)i, (int32_t)(n_maps + c - 1), ITEM_COMPOSE});
+    }
+    n_maps += K - 1;
+    ++n_heavy;
+  }
+  if (n_maps > 0x7FFFFFFF || n_heavy > 0x7FFFFFFF) return fail(FT_ERR_SHAPE, "too many chunks");
+  std::stable_sort(H.compose.begin(), H.compose.end(), [](const FItem& a, const FItem& b) { return a.len > b.len; });
+  std::stable_sort(light.begin(), light.end(), [](const FItem& a, const FItem& b) { return a.len > b.len; });
+  pad4(H.compose, ITEM_COMPOSE);
+  H.apply = head;
+  pad4(H.apply, ITEM_HEAD);
+  H.apply.insert(H.apply.end(), light.begin(), light.end());
+  pad4(H.apply, ITEM_LIGHT);
+
+  // combine levels: fold each heavy row's maps `fanin` at a time until one remains
+  const int64_t fan = P->fanin;
+  std::vector<int64_t> cur_off(heavy_base), cur_n(heavy_nmaps);
+  int64_t region_base[2] = {0, n_maps};
+  int level = 0;
+  int64_t out0 = 0;
+  std::vector<int64_t> active;
+  for (int64_t h = 0; h < n_heavy; ++h) active.push_back(h);
+  while (!active.empty()) {
+    std::vector<CItem> items;
+    std::vector<int64_t> next;
+    int64_t out_next = 0;
+    int dst = (level + 1) & 1;
+    for (int64_t h : active) {
+      int64_t n = cur_n[h], off = cur_off[h];
+      if (n <= fan) {
+        items.push_back(CItem{off, -1, (int32_t)n, (int32_t)heavy_rows[h], (int32_t)h, 0});
+        continue;
+      }
+      int64_t groups = (n + fan - 1) / fan;
+      int64_t base = region_base[dst] + out_next;
+      for (int64_t g = 0; g < groups; ++g)
+        items.push_back(CItem{off + g * fan, base + g, (int32_t)std::min(fan, n - g * fan), (int32_t)heavy_rows[h],
+                              (int32_t)h, 0});
+      out_next += groups;
+      cur_off[h] = base;
+      cur_n[h] = groups;
+      next.push_back(h);
+    }
+    if (level == 0) out0 = out_next;
+    if (out_next > (dst == 1 ? INT64_MAX : n_maps)) return fail(FT_ERR_STATE, "combine plan overflow");
+    H.levels.push_back(std::move(items));
+    active.swap(next);
+    ++level;
+  }
+
+  // segments for the core, loss and gradient passes
+  H.seg_ptr.assign((size_t)I + 1, 0);
+  for (int64_t i = 0; i < I; ++i) {
+    int64_t s = H.row_ptr[i], L = H.row_ptr[i + 1] - s;
+    for (int64_t o = 0; o < L; o += kSegLen)
+      H.segs.push_back(Seg{s + o, (int32_t)std::min<int64_t>(kSegLen, L - o), (int32_t)i});
+    H.seg_ptr[i + 1] = (int64_t)H.segs.size();
+  }
+
+  M.n_compose = (int64_t)H.compose.size();
+  M.n_apply = (int64_t)H.apply.size();
+  M.n_heavy = n_heavy;
+  M.n_maps = n_maps;
+  M.n_level_out0 = out0;
+  M.n_segs = (int64_t)H.segs.size();
+  int64_t off = 0;
+  for (auto& L : H.levels) {
+    M.level_off.push_back(off);
+    M.level_len.push_back((int64_t)L.size());
+    off += (int64_t)L.size();
+  }
+  ft_mode_info& inf = M.info;
+  inf.rows = I;
+  inf.nonempty_rows = nonempty;
+  inf.max_row = max_row;
+  inf.light_rows = (int64_t)light.size();
+  inf.heavy_rows = n_heavy;
+  inf.chunks = (int64_t)head.size() + n_maps;
+  inf.segments = M.n_segs;
+  inf.combine_levels = (int32_t)H.levels.size();
+  return FT_OK;
+}
+
+}  // namespace ft
+
+using namespace ft;
+
+extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32_t* coords, const float* vals) {
+  if (!out || !d) return fail(FT_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (d->order < 2 || d->order > FT_MAX_ORDER) return fail(FT_ERR_SHAPE, "order must be in 2..FT_MAX_ORDER");
+  if (d->nnz < 0 || d->nnz > (int64_t)0xFFFFFFFFLL) return fail(FT_ERR_SHAPE, "nnz out of range");
+  if (d->nnz > 0 && (!coords || !vals)) return fail(FT_ERR_ARG, "null coords or vals");
+  if (d->R < 1) return fail(FT_ERR_SHAPE, "R must be positive");
+  for (int n = 0; n < d->order; ++n) {
+    if (d->dims[n] < 1 || d->dims[n] > 0x7FFFFFFF) return fail(FT_ERR_SHAPE, "dimension out of range");
+    if (d->J[n] != d->J[0]) return fail(FT_ERR_UNSUPPORTED, "all J_n must be equal");
+  }
+  if (!supported(d->order, d->J[0], d->R))
+    return fail(FT_ERR_UNSUPPORTED, "no kernels compiled for order " + std::to_string(d->order) + ", J " +
+                                        std::to_string(d->J[0]) + ", R " + std::to_string(d->R));
+  if (d->chunk < 0 || d->fanin < 0 || d->fanin == 1) return fail(FT_ERR_ARG, "bad chunk or fanin");
+  if ((d->flags & FT_WITH_PERM) && d->nnz > 0x7FFFFFFF) return fail(FT_ERR_SHAPE, "FT_WITH_PERM needs nnz < 2^31");
+  const int N = d->order;
+  const int64_t nnz = d->nnz;
+  const int T = num_threads();
+  // index validation
+  std::atomic<int64_t> bad{-1};
+  {
+    const int64_t total = (int64_t)N * nnz, per = (total + T - 1) / T;
+    parallel_for(T, [&](int t) {
+      int64_t lo = t * per, hi = std::min(total, lo + per);
+      for (int64_t k = lo; k < hi; ++k) {
+        int64_t n = k / (nnz > 0 ? nnz : 1);
+        int32_t c = coords[k];
+        if (c < 0 || c >= d->dims[n]) {
+          bad.store(k);
+          return;
+        }
+      }
+    });
+  }
+  if (bad.load() >= 0) {
+    int64_t k = bad.load();
+    return fail(FT_ERR_INDEX, "coordinate out of range: mode " + std::to_string(k / nnz) + ", element " +
+                                  std::to_string(k % nnz) + ", value " + std::to_string(coords[k]));
+  }
+  ft_plan* P = new (std::nothrow) ft_plan();
+  if (!P) return fail(FT_ERR_NOMEM, "plan allocation failed");
+  P->desc = *d;
+  P->N = N;
+  P->J = d->J[0];
+  P->R = d->R;
+  P->nnz = nnz;
+  P->chunk = d->chunk ? d->chunk : 128;
+  P->fanin = d->fanin ? d->fanin : 64;
+  try {
+    P->meta.resize(N);
+    P->host.resize(N);
+    P->dev.resize(N);
+  } catch (const std::bad_alloc&) {
+    delete P;
+    return fail(FT_ERR_NOMEM, "plan allocation failed");
+  }
+  for (int m = 0; m < N; ++m) {
+    ft_status s = build_mode(P, m, coords, vals, T);
+    if (s != FT_OK) {
+      delete P;
+      return s;
+    }
+  }
+  P->host_valid = true;
+  *out = P;
+  return FT_OK;
+}
+
+namespace {
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& src, size_t& bytes) {
+  *dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  bytes += src.size() * sizeof(T);
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+template <class T>
+hipError_t alloc(T** dst, size_t count, size_t& bytes) {
+  *dst = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)dst, count * sizeof(T));
+  if (e == hipSuccess) bytes += count * sizeof(T);
+  return e;
+}
+void free_dev(ft_plan* P) {
+  for (auto& D : P->dev) {
+    (void)hipFree(D.row_ptr); (void)hipFree(D.idx); (void)hipFree(D.val); (void)hipFree(D.perm);
+    (void)hipFree(D.compose);
+    (void)hipFree(D.apply); (void)hipFree(D.levels); (void)hipFree(D.segs); (void)hipFree(D.seg_ptr);
+    D = ModeDev{};
+  }
+  (void)hipFree(P->maps); (void)hipFree(P->map_cnt); (void)hipFree(P->hvec); (void)hipFree(P->partials);
+  (void)hipFree(P->dpartials);
+  (void)hipFree(P->tseg); (void)hipFree(P->gbuf);
+  P->maps = nullptr; P->map_cnt = nullptr; P->hvec = nullptr; P->partials = nullptr; P->dpartials = nullptr;
+  P->tseg = nullptr; P->gbuf = nullptr;
+  P->device_bytes = 0;
+  P->uploaded = false;
+}
+}  // namespace
+
+extern "C" ft_status ft_plan_upload(ft_plan* P, void* stream) {
+  if (!P) return fail(FT_ERR_ARG, "null plan");
+  if (P->uploaded) return FT_OK;
+  if (!P->host_valid) return fail(FT_ERR_STATE, "host plan already released");
+  (void)stream;
+  size_t bytes = 0;
+  hipError_t e = hipSuccess;
+  int64_t max_slots = 1, max_heavy = 1, max_segs = 1;
+  for (int m = 0; m < P->N && e == hipSuccess; ++m) {
+    ModeHost& H = P->host[m];
+    ModeDev& D = P->dev[m];
+    ModeMeta& M = P->meta[m];
+    e = upload(&D.row_ptr, H.row_ptr, bytes);
+    if (e == hipSuccess) e = upload(&D.idx, H.idx, bytes);
+    if (e == hipSuccess) e = upload(&D.val, H.val, bytes);
+    if (e == hipSuccess && (P->desc.flags & FT_WITH_PERM)) {
+      std::vector<int32_t> p32(H.perm.begin(), H.perm.end());
+      e = upload(&D.perm, p32, bytes);
+    }
+    if (e == hipSuccess) e = upload(&D.compose, H.compose, bytes);
+    if (e == hipSuccess) e = upload(&D.apply, H.apply, bytes);
+    if (e == hipSuccess) {
+      std::vector<CItem> all;
+      for (auto& L : H.levels) all.insert(all.end(), L.begin(), L.end());
+      e = upload(&D.levels, all, bytes);
+    }
+    if (e == hipSuccess) e = upload(&D.segs, H.segs, bytes);
+    if (e == hipSuccess) e = upload(&D.seg_ptr, H.seg_ptr, bytes);
+    max_slots = std::max(max_slots, M.n_maps + M.n_level_out0);
+    max_heavy = std::max(max_heavy, M.n_heavy);
+    max_segs = std::max(max_segs, M.n_segs);
+  }
+  const int J = P->J, R = P->R;
+  if (e == hipSuccess) e = alloc(&P->maps, (size_t)max_slots * (J * J + J), bytes);
+  if (e == hipSuccess) e = alloc(&P->map_cnt, (size_t)max_slots, bytes);
+  if (e == hipSuccess) e = alloc(&P->hvec, (size_t)max_heavy * J, bytes);
+  if (e == hipSuccess) e = alloc(&P->partials, (size_t)kPartials * J * R, bytes);
+  if (e == hipSuccess) e = alloc(&P->dpartials, (size_t)kPartials * 2, bytes);
+  if (e == hipSuccess) e = alloc(&P->tseg, (size_t)max_segs * R, bytes);
+  if (e == hipSuccess) e = alloc(&P->gbuf, (size_t)J * R, bytes);
+  if (e != hipSuccess) {
+    free_dev(P);
+    return fail(FT_ERR_HIP, std::string("device allocation or copy failed: ") + hipGetErrorString(e));
+  }
+  for (int m = 0; m < P->N; ++m) P->dev[m].perm = (P->desc.flags & FT_WITH_PERM) ? P->dev[m].perm : nullptr;
+  P->device_bytes = bytes;
+  P->uploaded = true;
+  if (!(P->desc.flags & FT_KEEP_HOST)) {
+    for (auto& H : P->host) H = ModeHost{};
+    P->host_valid = false;
+  }
+  return FT_OK;
+}
+
+extern "C" void ft_plan_destroy(ft_plan* P) {
+  if (!P) return;
+  if (P->uploaded) {
+    (void)hipDeviceSynchronize();
+    free_dev(P);
+  }
+  delete P;
+}
+
+extern "C" ft_status ft_plan_mode_info(const ft_plan* P, int32_t mode, ft_mode_info* info) {
+  if (!P || !info) return fail(FT_ERR_ARG, "null argument");
+  if (mode < 0 || mode >= P->N) return fail(FT_ERR_ARG, "mode out of range");
+  *info = P->meta[mode].info;
+  return FT_OK;
+}
+
+extern "C" ft_status ft_plan_device_bytes(const ft_plan* P, size_t* bytes) {
+  if (!P || !bytes) return fail(FT_ERR_ARG, "null argument");
+  *bytes = P->device_bytes;
+  return FT_OK;
+}
+
+extern "C" ft_status ft_plan_host_csr(const ft_plan* P, int32_t mode, int64_t* row_ptr, int32_t* idx, float* vals,
+                                      int64_t* perm) {
+  if (!P) return fail(FT_ERR_ARG, "null plan");
+  if (mode < 0 || mode >= P->N) return fail(FT_ERR_ARG, "mode out of range");
+  if (!P->host_valid) return fail(FT_ERR_STATE, "host plan not kept (use FT_KEEP_HOST)");
+  const ModeHost& H = P->host[mode];
+  if (row_ptr) std::memcpy(row_ptr, H.row_ptr.data(), H.row_ptr.size() * sizeof(int64_t));
+  if (idx && !H.idx.empty()) std::memcpy(idx, H.idx.data(), H.idx.size() * sizeof(int32_t));
+  if (vals && !H.val.empty()) std::memcpy(vals, H.val.data(), H.val.size() * sizeof(float));
+  if (perm && !H.perm.empty()) std::memcpy(perm, H.perm.data(), H.perm.size() * sizeof(int64_t));
+  return FT_OK;
+}

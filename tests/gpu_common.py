@@ -1,0 +1,49 @@
+"""Shared setup for the GPU parity tests: one seeded problem, fed to both the oracle and the HIP path."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+import synth
+
+
+def make_problem(dims, nnz, zipf, J, R, seed, sigma=0.1, values="int1to5"):
+    c, _ = synth.coords(dims, nnz, zipf, seed)
+    v = synth.values(nnz, values, seed)
+    A, B = synth.init_params(dims, J, R, sigma, seed + 1)
+    return c, v, A, B
+
+
+def gpu_setup(dims, J, R, c, v, A, B, **plan_kw):
+    import paper_2210_06014_amd as ft
+
+    plan = ft.Plan(dims, J, R, c, v, **plan_kw)
+    prm = ft.Params(A, B)
+    ft.refresh(plan, prm)
+    return plan, prm
+
+
+def oracle_model(dims, J, R, c, v, A, B):
+    return oracle.Model(dims, J, R, c, v.astype(np.float64), [a.astype(np.float64) for a in A],
+                        [b.astype(np.float64) for b in B])
+
+
+def to_np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def abs_scale(C_list, coords):
+    """sum_r prod_n |C(n)[i_n, r]|: the natural scale of a rounding error in xhat."""
+    p = None
+    for n, C in enumerate(C_list):
+        rows = np.abs(C[coords[n]])
+        p = rows if p is None else p * rows
+    return p.sum(axis=1)
+
+
+def delta_ok(after_gpu, after_orc, before, rel=1e-3, abs_rel=1e-6):
+    """||gpu - oracle|| <= rel ||oracle - before|| + abs_rel ||oracle||; returns (ok, err, bound)."""
+    d = np.linalg.norm(after_orc - before)
+    err = np.linalg.norm(after_gpu - after_orc)
+    bound = rel * d + abs_rel * np.linalg.norm(after_orc)
+    return err <= bound, err, bound

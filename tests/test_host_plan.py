@@ -1,0 +1,106 @@
+"""Host logic of the C-ABI library (no GPU): exported symbols, plan construction, error codes."""
+import re
+import os
+
+import numpy as np
+import pytest
+
+import paper_2210_06014_amd as ft
+import synth
+from paper_2210_06014_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "fastertucker.h")).read()
+    declared = set(re.findall(r"\b(ft_[a-z0-9_]+)\s*\(", header))
+    assert declared == set(_lib.SYMBOLS)
+    lib = _lib.load()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_supported_table():
+    assert ft.supported(3, 16, 16)
+    assert ft.supported(3, 32, 32)
+    assert ft.supported(8, 8, 16)
+    assert not ft.supported(3, 12, 16)
+
+
+def _plan(dims, J, R, coords, vals, **kw):
+    return ft.Plan(dims, J, R, coords, vals, keep_host=True, upload=False, **kw)
+
+
+@pytest.mark.parametrize("order", [3, 4])
+def test_csr_order_and_permutation(order):
+    dims = [37, 23, 11, 7][:order]
+    J, R = (8, 8)
+    c, _ = synth.coords(dims, 2000, 1.1, seed=5)
+    v = synth.values(2000, "int1to5", seed=5)
+    # duplicate a few coordinates: the plan must keep every element
+    c = np.concatenate([c, c[:, :17]], axis=1)
+    v = np.concatenate([v, v[:17] + 1])
+    nnz = c.shape[1]
+    plan = _plan(dims, J, R, c, v, chunk=16)
+    for m in range(order):
+        row_ptr, idx, vals, perm = plan.host_csr(m)
+        assert row_ptr[0] == 0 and row_ptr[-1] == nnz
+        np.testing.assert_array_equal(np.diff(row_ptr), np.bincount(c[m], minlength=dims[m]))
+        assert sorted(perm.tolist()) == list(range(nnz))
+        np.testing.assert_array_equal(vals, v[perm])
+        for k in range(order - 1):
+            np.testing.assert_array_equal(idx[k], c[(m + 1 + k) % order][perm])
+        # lexicographic (i_m, i_{m+1}, ..., i_{m-1}); ties keep input order (stable)
+        keys = [c[(m + k) % order][perm] for k in range(order)]
+        key_tuples = list(zip(*keys, perm))
+        assert key_tuples == sorted(key_tuples)
+        info = plan.mode_info(m)
+        counts = np.diff(row_ptr)
+        assert info["light_rows"] == int(np.sum((counts > 0) & (counts <= 16)))
+        assert info["heavy_rows"] == int(np.sum(counts > 16))
+        assert info["chunks"] == int(np.sum(np.where(counts > 16, (counts + 15) // 16, 0)))
+        assert info["max_row"] == int(counts.max())
+
+
+def test_errors():
+    dims = [10, 10, 10]
+    c, _ = synth.coords(dims, 100, 0.0, seed=1)
+    v = np.ones(100, dtype=np.float32)
+    bad = c.copy()
+    bad[1, 57] = 10
+    with pytest.raises(ft.FtError) as e:
+        _plan(dims, 8, 8, bad, v)
+    assert e.value.status == 3 and "element 57" in str(e.value)
+    bad[1, 57] = -1
+    with pytest.raises(ft.FtError) as e:
+        _plan(dims, 8, 8, bad, v)
+    assert e.value.status == 3
+    with pytest.raises(ft.FtError) as e:
+        _plan(dims, 12, 8, c, v)
+    assert e.value.status == 4
+    with pytest.raises(ft.FtError) as e:
+        _plan(dims, [8, 8, 16], 8, c, v)
+    assert e.value.status == 4
+    with pytest.raises(ft.FtError) as e:
+        _plan([10], 8, 8, c[:1], v)
+    assert e.value.status == 2
+    with pytest.raises(ft.FtError) as e:
+        _plan([10, 0, 10], 8, 8, c, v)
+    assert e.value.status == 2
+
+
+def test_empty_tensor_plan():
+    plan = _plan([5, 6, 7], 8, 8, np.zeros((3, 0), dtype=np.int32), np.zeros(0, dtype=np.float32))
+    row_ptr, idx, vals, perm = plan.host_csr(0)
+    assert row_ptr.sum() == 0 and idx.size == 0
+    assert plan.mode_info(1)["nonempty_rows"] == 0
+
+
+def test_calls_before_upload_fail_cleanly():
+    c, _ = synth.coords([10, 10, 10], 50, 0.0, seed=1)
+    plan = _plan([10, 10, 10], 8, 8, c, np.ones(50, dtype=np.float32))
+    lib = _lib.load()
+    st = lib.ft_factor_pass(plan.handle, None, 0, 1e-3, 1e-2, None)
+    assert st == 5  # FT_ERR_STATE: not uploaded
+    assert b"not uploaded" in lib.ft_last_error()
