@@ -157,11 +157,15 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
 #pragma unroll
     for (int r = 0; r < R; ++r) Bw[e][r] = j < J ? Bm[j * R + r] : 0.f;
   }
-  float a[E];
+  // The row is carried in FP64 registers and rounded to FP32 once when
+  // stored: the decay step lr*lam*a is about a hundred ulps of a, nearly the
+  // same every step, so FP32 rounding of the running state would accumulate
+  // coherently (up to k/2 ulps after k steps) instead of averaging out.
+  double a[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int j = l + 16 * e;
-    a[e] = (it.len > 0 && j < J) ? Am[(int64_t)it.row * J + j] : 0.f;
+    a[e] = (it.len > 0 && j < J) ? (double)Am[(int64_t)it.row * J + j] : 0.0;
   }
   int maxlen = it.len;
   maxlen = max(maxlen, __shfl_xor(maxlen, 16));
@@ -181,15 +185,15 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
       shared_g<J, R>(Bw, w[s], g);
       float pr = 0.f;
 #pragma unroll
-      for (int e = 0; e < E; ++e) pr = fmaf(a[e], g[e], pr);
+      for (int e = 0; e < E; ++e) pr = fmaf((float)a[e], g[e], pr);
       pr = group_sum<16>(pr);
       const float es = bcast16<s>(xv) - pr;
-      const float dec = (t0 + s) < it.len ? c1 : 0.f;
-      const float le = lr * es;
+      const double dec = (t0 + s) < it.len ? (double)c1 : 0.0;
+      const double le = (double)(lr * es);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        a[e] = fmaf(dec, a[e], a[e]);
-        a[e] = fmaf(le, g[e], a[e]);
+        a[e] = fma(dec, a[e], a[e]);
+        a[e] = fma(le, (double)g[e], a[e]);
       }
     });
   }
@@ -199,9 +203,9 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
       const int j = l + 16 * e;
       if (j < J) {
         if (it.kind == ITEM_LIGHT)
-          Am[(int64_t)it.row * J + j] = a[e];
+          Am[(int64_t)it.row * J + j] = (float)a[e];
         else
-          hvec[(int64_t)it.slot * J + j] = a[e];
+          hvec[(int64_t)it.slot * J + j] = (float)a[e];
       }
     }
   }
