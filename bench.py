@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=3_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--chunk", type=int, default=0, help="rows longer than this are split (0: library default)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -121,7 +122,7 @@ def main():
     c, v, A, B = synth.make(w, nnz=nnz)
     log(f"generated in {time.time() - t:.1f} s")
     t = time.time()
-    plan = ft.Plan(w.dims, J, R, c, v)
+    plan = ft.Plan(w.dims, J, R, c, v, chunk=args.chunk)
     log(f"plan built and uploaded in {time.time() - t:.1f} s ({plan.device_bytes() / 2**30:.2f} GiB on device)")
     prm = ft.Params(A, B)
     ft.refresh(plan, prm)
@@ -153,7 +154,7 @@ def main():
 
     value = 2 * N * nnz / (ms_step / 1e3)
     counts = [np.bincount(c[m], minlength=w.dims[m]) for m in range(N)]
-    alg = algorithmic(w, nnz, counts, 128)
+    alg = algorithmic(w, nnz, counts, args.chunk or 512)
     kernels = {}
     for k, (ms, n) in prof.items():
         if n == 0:

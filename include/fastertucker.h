@@ -62,7 +62,7 @@ typedef struct {
   int32_t J[FT_MAX_ORDER];      /* factor rank per mode; must all be equal */
   int32_t R;                    /* core rank */
   int64_t nnz;                  /* |Omega|, 0..2^32-1 */
-  int32_t chunk;                /* rows with more elements are split into chunks of this many (0: 128) */
+  int32_t chunk;                /* rows with more elements are split into chunks of this many (0: 512) */
   int32_t fanin;                /* chunk maps folded per combine step (0: 64) */
   int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM */
 } ft_desc;

@@ -54,6 +54,62 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
+
+// Fused broadcast-multiply-accumulate: v_fmac_f32_dpp with row_newbcast
+// reads src from lane i of the 16-lane row as its first operand, so one
+// instruction does what a DPP move plus an FMA would.  The compiler does not
+// form these, hence inline assembly.  Each block opens with s_nop 4: five
+// wait states cover both DPP hazards of this ISA (a VALU write of the DPP
+// source VGPR needs two, a VALU write of EXEC needs five); inside a block no
+// instruction writes a register that a later DPP operand of the block reads.
+#define FT_BC(n) " row_newbcast:" #n " row_mask:0xf bank_mask:0xf\n\t"
+#define FT_DOT(n, op) "v_fmac_f32_dpp %0, %1, %" #op FT_BC(n)
+#define FT_AXPY(n, op) "v_fmac_f32_dpp %" #op ", %16, %17" FT_BC(n)
+#define FT_AXPY8(n, op) "v_fmac_f32_dpp %" #op ", %8, %9" FT_BC(n)
+
+// acc += sum_{i<16} src[lane i] * v[i]
+__device__ __forceinline__ void dot_bcast16(float& acc, float src, const float* v) {
+  asm volatile("s_nop 4\n\t" FT_DOT(0, 2) FT_DOT(1, 3) FT_DOT(2, 4) FT_DOT(3, 5) FT_DOT(4, 6) FT_DOT(5, 7)
+                   FT_DOT(6, 8) FT_DOT(7, 9) FT_DOT(8, 10) FT_DOT(9, 11) FT_DOT(10, 12) FT_DOT(11, 13)
+                       FT_DOT(12, 14) FT_DOT(13, 15) FT_DOT(14, 16) FT_DOT(15, 17)
+               : "+v"(acc)
+               : "v"(src), "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]),
+                 "v"(v[8]), "v"(v[9]), "v"(v[10]), "v"(v[11]), "v"(v[12]), "v"(v[13]), "v"(v[14]), "v"(v[15]));
+}
+// acc += sum_{i<8} src[lane i] * v[i]
+__device__ __forceinline__ void dot_bcast8(float& acc, float src, const float* v) {
+  asm volatile("s_nop 4\n\t" FT_DOT(0, 2) FT_DOT(1, 3) FT_DOT(2, 4) FT_DOT(3, 5) FT_DOT(4, 6) FT_DOT(5, 7)
+                   FT_DOT(6, 8) FT_DOT(7, 9)
+               : "+v"(acc)
+               : "v"(src), "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]));
+}
+// v[i] += src[lane i] * t, i < 16
+__device__ __forceinline__ void axpy_bcast16(float* v, float src, float t) {
+  asm volatile("s_nop 4\n\t" FT_AXPY(0, 0) FT_AXPY(1, 1) FT_AXPY(2, 2) FT_AXPY(3, 3) FT_AXPY(4, 4) FT_AXPY(5, 5)
+                   FT_AXPY(6, 6) FT_AXPY(7, 7) FT_AXPY(8, 8) FT_AXPY(9, 9) FT_AXPY(10, 10) FT_AXPY(11, 11)
+                       FT_AXPY(12, 12) FT_AXPY(13, 13) FT_AXPY(14, 14) FT_AXPY(15, 15)
+               : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7]),
+                 "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]), "+v"(v[14]), "+v"(v[15])
+               : "v"(src), "v"(t));
+}
+// v[i] += src[lane i] * t, i < 8
+__device__ __forceinline__ void axpy_bcast8(float* v, float src, float t) {
+  asm volatile("s_nop 4\n\t" FT_AXPY8(0, 0) FT_AXPY8(1, 1) FT_AXPY8(2, 2) FT_AXPY8(3, 3) FT_AXPY8(4, 4)
+                   FT_AXPY8(5, 5) FT_AXPY8(6, 6) FT_AXPY8(7, 7)
+               : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7])
+               : "v"(src), "v"(t));
+}
+template <int K>
+__device__ __forceinline__ void dot_bcast(float& acc, float src, const float* v) {
+  static_assert(K == 8 || K == 16, "row broadcasts cover 8 or 16 lanes");
+  if constexpr (K == 16) dot_bcast16(acc, src, v); else dot_bcast8(acc, src, v);
+}
+template <int K>
+__device__ __forceinline__ void axpy_bcast(float* v, float src, float t) {
+  static_assert(K == 8 || K == 16, "row broadcasts cover 8 or 16 lanes");
+  if constexpr (K == 16) axpy_bcast16(v, src, t); else axpy_bcast8(v, src, t);
+}
+
 template <int N>
 struct CPtrs {
   const float* p[N > 1 ? N - 1 : 1];
@@ -124,18 +180,19 @@ __device__ __forceinline__ void gather_w(const CPtrs<N>& cp, const int (&ix)[N >
   });
 }
 
+// g = B(m) w for this lane's elements j = l + 16 e; w_r comes from lane r % 16.
 template <int J, int R>
 __device__ __forceinline__ void shared_g(const float (&Bw)[J >= 16 ? J / 16 : 1][R], const float (&ws)[R >= 16 ? R / 16 : 1],
                                          float (&g)[J >= 16 ? J / 16 : 1]) {
   constexpr int E = J >= 16 ? J / 16 : 1;
+  constexpr int RE = R >= 16 ? R / 16 : 1;
+  constexpr int RK = R >= 16 ? 16 : R;
 #pragma unroll
-  for (int e = 0; e < E; ++e) g[e] = 0.f;
-  static_for<0, R>([&](auto Rr) {
-    constexpr int r = decltype(Rr)::value;
-    const float wr = bcast16<r % 16>(ws[r / 16]);
+  for (int e = 0; e < E; ++e) {
+    g[e] = 0.f;
 #pragma unroll
-    for (int e = 0; e < E; ++e) g[e] = fmaf(Bw[e][r], wr, g[e]);
-  });
+    for (int q = 0; q < RE; ++q) dot_bcast<RK>(g[e], ws[q], &Bw[e][16 * q]);
+  }
 }
 
 template <int N, int J, int R>
@@ -261,19 +318,16 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
       constexpr int s = decltype(S)::value;
       float g[E];
       shared_g<J, R>(Bw, w[s], g);
-      float gb[J];
-      static_for<0, J>([&](auto Ii) {
-        constexpr int i = decltype(Ii)::value;
-        gb[i] = bcast16<i % 16>(g[i / 16]);
-      });
+      constexpr int JK = J >= 16 ? 16 : J;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
+        // h = g_j + sum_i Nm[i][j] g_i ;  Nm[:, j] -= gp * h * g
         float h = g[e];
 #pragma unroll
-        for (int i = 0; i < J; ++i) h = fmaf(Nc[e][i], gb[i], h);
+        for (int q = 0; q < E; ++q) dot_bcast<JK>(h, g[q], &Nc[e][16 * q]);
         const float t = -gp * h;
 #pragma unroll
-        for (int i = 0; i < J; ++i) Nc[e][i] = fmaf(t, gb[i], Nc[e][i]);
+        for (int q = 0; q < E; ++q) axpy_bcast<JK>(&Nc[e][16 * q], g[q], t);
       }
       float pr = 0.f;
 #pragma unroll
@@ -474,19 +528,33 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
     partials[(int64_t)blockIdx.x * J * R + e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
 
-// Sum of the workgroup partials in a fixed order; optionally the core step
-// B <- B + lr (G / |Omega| - lam B) (Algorithm 5).
-__global__ __launch_bounds__(256) void k_reduce_update(const float* __restrict__ partials, int nparts, int JR,
-                                                       float* __restrict__ Bm, float* __restrict__ Gout, float lr,
-                                                       float lam, float inv_nnz, int update) {
+// Sum of the workgroup partials in a fixed order, in two stages: first every
+// block of kFold consecutive partials (many workgroups), then the blocks.
+constexpr int kFold = 32;
+
+__global__ __launch_bounds__(256) void k_fold_partials(const float* __restrict__ partials, int nparts, int JR,
+                                                       float* __restrict__ folded) {
+  const int b0 = blockIdx.x * kFold;
+  const int nb = min(kFold, nparts - b0);
   for (int e = threadIdx.x; e < JR; e += blockDim.x) {
     float s = 0.f;
-    for (int b = 0; b < nparts; ++b) s += partials[(int64_t)b * JR + e];
-    if (Gout) Gout[e] = s;
-    if (update) {
-      const float b = Bm[e];
-      Bm[e] = b + lr * (s * inv_nnz - lam * b);
-    }
+    for (int b = 0; b < nb; ++b) s += partials[(int64_t)(b0 + b) * JR + e];
+    folded[(int64_t)blockIdx.x * JR + e] = s;
+  }
+}
+
+// Final sum; optionally the core step B <- B + lr (G / |Omega| - lam B) (Algorithm 5).
+__global__ __launch_bounds__(256) void k_reduce_update(const float* __restrict__ folded, int nfold, int JR,
+                                                       float* __restrict__ Bm, float* __restrict__ Gout, float lr,
+                                                       float lam, float inv_nnz, int update) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= JR) return;
+  float s = 0.f;
+  for (int b = 0; b < nfold; ++b) s += folded[(int64_t)b * JR + e];
+  if (Gout) Gout[e] = s;
+  if (update) {
+    const float b = Bm[e];
+    Bm[e] = b + lr * (s * inv_nnz - lam * b);
   }
 }
 
@@ -643,6 +711,18 @@ hipError_t factor_impl(const ft_plan* P, int m, const ft_params* p, double lr, d
   return hipGetLastError();
 }
 
+hipError_t reduce_partials(const ft_plan* P, int nparts, float* Bm, float* Gout, float lr, float lam, float inv,
+                           int update, hipStream_t s) {
+  KTimer tm(P, FT_K_REDUCE, s);
+  const int JR = P->J * P->R;
+  const int nfold = (nparts + kFold - 1) / kFold;
+  float* folded = P->partials + (int64_t)kPartials * JR;
+  if (nfold > 0) hipLaunchKernelGGL(k_fold_partials, dim3(nfold), dim3(256), 0, s, P->partials, nparts, JR, folded);
+  hipLaunchKernelGGL(k_reduce_update, dim3((JR + 255) / 256), dim3(256), 0, s, folded, nfold, JR, Bm, Gout, lr, lam,
+                     inv, update);
+  return hipGetLastError();
+}
+
 int seg_blocks(int64_t nseg) {
   int64_t b = (nseg + 3) / 4;
   if (b > kPartials) b = kPartials;
@@ -760,12 +840,7 @@ hipError_t launch_core_grad(const ft_plan* P, int m, const ft_params* p, hipStre
   int nb = 0;
   hipError_t e = segsum(P, m, p, 0, nullptr, nullptr, s, &nb);
   if (e != hipSuccess) return e;
-  {
-    KTimer tm(P, FT_K_REDUCE, s);
-    hipLaunchKernelGGL(k_reduce_update, dim3(1), dim3(256), 0, s, P->partials, nb, P->J * P->R, nullptr, P->gbuf,
-                       0.f, 0.f, 0.f, 0);
-  }
-  return hipGetLastError();
+  return reduce_partials(P, nb, nullptr, P->gbuf, 0.f, 0.f, 0.f, 0, s);
 }
 
 hipError_t launch_core_update(const ft_plan* P, int m, const ft_params* p, double lr, double lam, float* G_out,
@@ -774,10 +849,7 @@ hipError_t launch_core_update(const ft_plan* P, int m, const ft_params* p, doubl
   hipError_t e = segsum(P, m, p, 0, nullptr, nullptr, s, &nb);
   if (e != hipSuccess) return e;
   const float inv = P->nnz > 0 ? (float)(1.0 / (double)P->nnz) : 0.f;
-  KTimer tm(P, FT_K_REDUCE, s);
-  hipLaunchKernelGGL(k_reduce_update, dim3(1), dim3(256), 0, s, P->partials, nb, P->J * P->R, p->B[m], G_out,
-                     (float)lr, (float)lam, inv, P->nnz > 0 ? 1 : 0);
-  return hipGetLastError();
+  return reduce_partials(P, nb, p->B[m], G_out, (float)lr, (float)lam, inv, P->nnz > 0 ? 1 : 0, s);
 }
 
 hipError_t launch_loss(const ft_plan* P, const ft_params* p, double lam_a, double lam_b, double* out4, hipStream_t s) {
@@ -829,9 +901,7 @@ hipError_t launch_grad(const ft_plan* P, const ft_params* p, const float* up, fl
 #undef X
       default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_reduce_update, dim3(1), dim3(256), 0, s, P->partials, nb, P->J * P->R, nullptr, gB[m], 0.f,
-                       0.f, 0.f, 0);
-    e = hipGetLastError();
+    e = reduce_partials(P, nb, nullptr, gB[m], 0.f, 0.f, 0.f, 0, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

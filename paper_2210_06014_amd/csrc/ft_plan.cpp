@@ -283,7 +283,7 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
   P->J = d->J[0];
   P->R = d->R;
   P->nnz = nnz;
-  P->chunk = d->chunk ? d->chunk : 128;
+  P->chunk = d->chunk ? d->chunk : 512;
   P->fanin = d->fanin ? d->fanin : 64;
   try {
     P->meta.resize(N);
@@ -376,7 +376,7 @@ extern "C" ft_status ft_plan_upload(ft_plan* P, void* stream) {
   if (e == hipSuccess) e = alloc(&P->maps, (size_t)max_slots * (J * J + J), bytes);
   if (e == hipSuccess) e = alloc(&P->map_cnt, (size_t)max_slots, bytes);
   if (e == hipSuccess) e = alloc(&P->hvec, (size_t)max_heavy * J, bytes);
-  if (e == hipSuccess) e = alloc(&P->partials, (size_t)kPartials * J * R, bytes);
+  if (e == hipSuccess) e = alloc(&P->partials, (size_t)(kPartials + kPartials / 32 + 1) * J * R, bytes);
   if (e == hipSuccess) e = alloc(&P->dpartials, (size_t)kPartials * 2, bytes);
   if (e == hipSuccess) e = alloc(&P->tseg, (size_t)max_segs * R, bytes);
   if (e == hipSuccess) e = alloc(&P->gbuf, (size_t)J * R, bytes);
