@@ -81,6 +81,24 @@ def cpu_baseline(w, c, v, A, B, sample):
     }
 
 
+def copy_calibration(nbytes):
+    """A plain copy kernel of known size: what FETCH_SIZE / WRITE_SIZE read for it calibrates the counters."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(3):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 3
+    print(json.dumps({"copy_bytes": nbytes, "ms_per_copy": ms, "GBps_read_plus_write": 2 * nbytes / ms / 1e6}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,7 +110,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--chunk", type=int, default=0, help="rows longer than this are split (0: library default)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_bytes:
+        return copy_calibration(args.copy_bytes)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -228,12 +228,13 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
   maxlen = max(maxlen, __shfl_xor(maxlen, 16));
   maxlen = max(maxlen, __shfl_xor(maxlen, 32));
   for (int t0 = 0; t0 < maxlen; t0 += 16) {
-    const bool vld = (t0 + l) < it.len;
-    const int64_t p = it.start + t0 + l;
+    // past the end: clamp to the item's last element (valid address); those
+    // steps are neutralised below (w = 0, no decay)
+    const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
     int ix[N - 1];
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) ix[k] = vld ? idx[(int64_t)k * nnz + p] : 0;
-    const float xv = vld ? val[p] : 0.f;
+    for (int k = 0; k < N - 1; ++k) ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] : 0;
+    const float xv = it.len > 0 ? val[p] : 0.f;
     float w[16][RE];
     gather_w<N, R>(cp, ix, l, t0, it.len, w);
     static_for<0, 16>([&](auto S) {
@@ -306,12 +307,13 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
   maxlen = max(maxlen, __shfl_xor(maxlen, 16));
   maxlen = max(maxlen, __shfl_xor(maxlen, 32));
   for (int t0 = 0; t0 < maxlen; t0 += 16) {
-    const bool vld = (t0 + l) < it.len;
-    const int64_t p = it.start + t0 + l;
+    // past the end: clamp to the item's last element (valid address); those
+    // steps are neutralised below (w = 0, no decay)
+    const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
     int ix[N - 1];
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) ix[k] = vld ? idx[(int64_t)k * nnz + p] : 0;
-    const float xv = vld ? val[p] : 0.f;
+    for (int k = 0; k < N - 1; ++k) ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] : 0;
+    const float xv = it.len > 0 ? val[p] : 0.f;
     float w[16][RE];
     gather_w<N, R>(cp, ix, l, t0, it.len, w);
     static_for<0, 16>([&](auto S) {
@@ -441,17 +443,19 @@ __global__ __launch_bounds__(256) void k_combine(const CItem* __restrict__ items
 // Segment passes (core gradient, loss, forward, gradient).  A wavefront takes
 // segments gw, gw + nw, ... (a fixed assignment), R/4 lanes per element.
 
+constexpr int kUnroll = 4;
+
+// prod over the gathered 16-byte slices of C rows.  Invalid slots carry index
+// 0 (a valid row) and are zeroed after the loads, so that the loads need no
+// branch and all of them can be in flight together.
 template <int N, int R>
-__device__ __forceinline__ floatx4 gather_w4(const CPtrs<N>& cp, const int32_t* __restrict__ idx, int64_t nnz,
-                                             int64_t p, bool vld, int q) {
-  floatx4 w = {1.f, 1.f, 1.f, 1.f};
+__device__ __forceinline__ floatx4 gather_row_product(const CPtrs<N>& cp, const int32_t (&ik)[N > 1 ? N - 1 : 1],
+                                                      bool vld, int q) {
+  floatx4 w = *reinterpret_cast<const floatx4*>(cp.p[0] + (int64_t)ik[0] * R + 4 * q);
 #pragma unroll
-  for (int k = 0; k < N - 1; ++k) {
-    const int32_t ik = vld ? idx[(int64_t)k * nnz + p] : 0;
-    const floatx4 c = *reinterpret_cast<const floatx4*>(cp.p[k] + (int64_t)ik * R + 4 * q);
-    w *= c;
-  }
-  return w;
+  for (int k = 1; k < N - 1; ++k) w *= *reinterpret_cast<const floatx4*>(cp.p[k] + (int64_t)ik[k] * R + 4 * q);
+  const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+  return vld ? w : zero;
 }
 
 // MODE 0: s = sum e w (core gradient); MODE 1: t = sum -e w (gradient of 1/2 sum e^2);
@@ -480,26 +484,47 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
     floatx4 crow = {0.f, 0.f, 0.f, 0.f};
     if (MODE != 2) crow = *reinterpret_cast<const floatx4*>(Cm + (int64_t)S.row * R + 4 * q);
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int t0 = 0; t0 < S.len; t0 += P) {
-      const bool vld = (t0 + slot) < S.len;
-      const int64_t p = S.start + t0 + slot;
-      const floatx4 w = gather_w4<N, R>(cp, idx, nnz, p, vld, q);
-      float d;
-      if (MODE == 2) {
-        d = vld ? up[perm[p]] : 0.f;
-      } else {
-        float xh = crow[0] * w[0];
-        xh = fmaf(crow[1], w[1], xh);
-        xh = fmaf(crow[2], w[2], xh);
-        xh = fmaf(crow[3], w[3], xh);
-        xh = group_sum<QL>(xh);
-        const float x = vld ? val[p] : 0.f;
-        d = vld ? (MODE == 0 ? x - xh : xh - x) : 0.f;
+    // U element groups per trip: all index loads, then all gathers, then the
+    // arithmetic, so that each wavefront keeps U times more loads in flight.
+    for (int t0 = 0; t0 < S.len; t0 += P * kUnroll) {
+      bool vl[kUnroll];
+      int64_t pp[kUnroll];
+      int32_t ik[kUnroll][N - 1];
+      float xv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        // positions past the end are clamped to the last element (a valid
+        // address) so that the loads need no branch; their terms are zeroed
+        vl[u] = (t0 + u * P + slot) < S.len;
+        pp[u] = S.start + min(t0 + u * P + slot, S.len - 1);
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) ik[u][k] = idx[(int64_t)k * nnz + pp[u]];
+        if (MODE == 2)
+          xv[u] = up[perm[pp[u]]];
+        else
+          xv[u] = val[pp[u]];
       }
-      acc[0] = fmaf(d, w[0], acc[0]);
-      acc[1] = fmaf(d, w[1], acc[1]);
-      acc[2] = fmaf(d, w[2], acc[2]);
-      acc[3] = fmaf(d, w[3], acc[3]);
+      floatx4 w[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) w[u] = gather_row_product<N, R>(cp, ik[u], vl[u], q);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        float d;
+        if (MODE == 2) {
+          d = vl[u] ? xv[u] : 0.f;
+        } else {
+          float xh = crow[0] * w[u][0];
+          xh = fmaf(crow[1], w[u][1], xh);
+          xh = fmaf(crow[2], w[u][2], xh);
+          xh = fmaf(crow[3], w[u][3], xh);
+          xh = group_sum<QL>(xh);
+          d = vl[u] ? (MODE == 0 ? xv[u] - xh : xh - xv[u]) : 0.f;
+        }
+        acc[0] = fmaf(d, w[u][0], acc[0]);
+        acc[1] = fmaf(d, w[u][1], acc[1]);
+        acc[2] = fmaf(d, w[u][2], acc[2]);
+        acc[3] = fmaf(d, w[u][3], acc[3]);
+      }
     }
 #pragma unroll
     for (int off = QL; off < 64; off <<= 1)
@@ -596,19 +621,34 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
   for (int64_t sg = (int64_t)blockIdx.x * 4 + wave; sg < nseg; sg += nw) {
     const Seg S = segs[sg];
     const floatx4 crow = *reinterpret_cast<const floatx4*>(Cm + (int64_t)S.row * R + 4 * q);
-    for (int t0 = 0; t0 < S.len; t0 += P) {
-      const bool vld = (t0 + slot) < S.len;
-      const int64_t p = S.start + t0 + slot;
-      const floatx4 w = gather_w4<N, R>(cp, idx, nnz, p, vld, q);
-      float xh = crow[0] * w[0];
-      xh = fmaf(crow[1], w[1], xh);
-      xh = fmaf(crow[2], w[2], xh);
-      xh = fmaf(crow[3], w[3], xh);
-      xh = group_sum<QL>(xh);
-      if (vld && q == 0) {
-        const float e = val[p] - xh;
-        sse += (double)e * (double)e;
-        if (out) out[perm[p]] = xh;
+    for (int t0 = 0; t0 < S.len; t0 += P * kUnroll) {
+      bool vl[kUnroll];
+      int64_t pp[kUnroll];
+      int32_t ik[kUnroll][N - 1];
+      float xv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        vl[u] = (t0 + u * P + slot) < S.len;
+        pp[u] = S.start + min(t0 + u * P + slot, S.len - 1);
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) ik[u][k] = idx[(int64_t)k * nnz + pp[u]];
+        xv[u] = val[pp[u]];
+      }
+      floatx4 w[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) w[u] = gather_row_product<N, R>(cp, ik[u], vl[u], q);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        float xh = crow[0] * w[u][0];
+        xh = fmaf(crow[1], w[u][1], xh);
+        xh = fmaf(crow[2], w[u][2], xh);
+        xh = fmaf(crow[3], w[u][3], xh);
+        xh = group_sum<QL>(xh);
+        if (vl[u] && q == 0) {
+          const float e = xv[u] - xh;
+          sse += (double)e * (double)e;
+          if (out) out[perm[pp[u]]] = xh;
+        }
       }
     }
   }
@@ -636,19 +676,33 @@ __global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ X, int6
   if (threadIdx.x == 0) dpart[blockIdx.x] = red[0];
 }
 
-constexpr int kSumsqBlocks = 32;
+constexpr int kSumsqBlocks = 256;
 
-__global__ void k_loss_finish(const double* __restrict__ dpart, int n_sse, const double* __restrict__ rpart,
-                              int n_a, int n_b, double nnz, double lam_a, double lam_b, double* __restrict__ out4) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Fixed-order FP64 sums of the partials (strided per thread, then a tree).
+__global__ __launch_bounds__(256) void k_loss_finish(const double* __restrict__ dpart, int n_sse,
+                                                     const double* __restrict__ rpart, int n_a, int n_b, double nnz,
+                                                     double lam_a, double lam_b, double* __restrict__ out4) {
+  __shared__ double red[3][256];
+  const int t = threadIdx.x;
   double sse = 0.0, ra = 0.0, rb = 0.0;
-  for (int k = 0; k < n_sse; ++k) sse += dpart[k];
-  for (int k = 0; k < n_a; ++k) ra += rpart[k];
-  for (int k = 0; k < n_b; ++k) rb += rpart[n_a + k];
-  out4[0] = sse;
-  out4[1] = nnz > 0 ? sqrt(sse / nnz) : 0.0;
-  out4[2] = lam_a * ra;
-  out4[3] = lam_b * rb;
+  for (int k = t; k < n_sse; k += 256) sse += dpart[k];
+  for (int k = t; k < n_a; k += 256) ra += rpart[k];
+  for (int k = t; k < n_b; k += 256) rb += rpart[n_a + k];
+  red[0][t] = sse;
+  red[1][t] = ra;
+  red[2][t] = rb;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h)
+      for (int c = 0; c < 3; ++c) red[c][t] += red[c][t + h];
+    __syncthreads();
+  }
+  if (t == 0) {
+    out4[0] = red[0][0];
+    out4[1] = nnz > 0 ? sqrt(red[0][0] / nnz) : 0.0;
+    out4[2] = lam_a * red[1][0];
+    out4[3] = lam_b * red[2][0];
+  }
 }
 
 // Predictions for query coordinates (structure of arrays [N][q]).
@@ -758,10 +812,13 @@ hipError_t loss_impl(const ft_plan* P, const ft_params* p, double lam_a, double 
   const ModeDev& D = P->dev[0];
   const CPtrs<N> cp = others<N>(p, 0);
   const int nb = seg_blocks(M.n_segs);
-  KTimer tm(P, FT_K_LOSS, s);
-  hipLaunchKernelGGL((k_loss<N, R>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp, p->C[0],
-                     out4 ? P->dpartials : nullptr, D.perm, xout);
+  {
+    KTimer tm(P, FT_K_LOSS, s);
+    hipLaunchKernelGGL((k_loss<N, R>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp,
+                       p->C[0], out4 ? P->dpartials : nullptr, D.perm, xout);
+  }
   if (!out4) return hipGetLastError();
+  KTimer tm(P, FT_K_REDUCE, s);
   double* rpart = P->dpartials + kPartials;
   for (int n = 0; n < N; ++n)
     hipLaunchKernelGGL(k_sumsq, dim3(kSumsqBlocks), dim3(256), 0, s, p->A[n], P->desc.dims[n] * J,
@@ -769,7 +826,7 @@ hipError_t loss_impl(const ft_plan* P, const ft_params* p, double lam_a, double 
   for (int n = 0; n < N; ++n)
     hipLaunchKernelGGL(k_sumsq, dim3(kSumsqBlocks), dim3(256), 0, s, p->B[n], (int64_t)J * R,
                        rpart + (N + n) * kSumsqBlocks);
-  hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(64), 0, s, P->dpartials, nb, rpart, N * kSumsqBlocks,
+  hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, s, P->dpartials, nb, rpart, N * kSumsqBlocks,
                      N * kSumsqBlocks, (double)P->nnz, lam_a, lam_b, out4);
   return hipGetLastError();
 }

@@ -377,7 +377,7 @@ extern "C" ft_status ft_plan_upload(ft_plan* P, void* stream) {
   if (e == hipSuccess) e = alloc(&P->map_cnt, (size_t)max_slots, bytes);
   if (e == hipSuccess) e = alloc(&P->hvec, (size_t)max_heavy * J, bytes);
   if (e == hipSuccess) e = alloc(&P->partials, (size_t)(kPartials + kPartials / 32 + 1) * J * R, bytes);
-  if (e == hipSuccess) e = alloc(&P->dpartials, (size_t)kPartials * 2, bytes);
+  if (e == hipSuccess) e = alloc(&P->dpartials, (size_t)kPartials + 2 * FT_MAX_ORDER * 256, bytes);
   if (e == hipSuccess) e = alloc(&P->tseg, (size_t)max_segs * R, bytes);
   if (e == hipSuccess) e = alloc(&P->gbuf, (size_t)J * R, bytes);
   if (e != hipSuccess) {
