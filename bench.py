@@ -81,6 +81,28 @@ def cpu_baseline(w, c, v, A, B, sample):
     }
 
 
+COUNTER_FILES = {"netflix": "profiles/netflix_j16_fp32_hbm_counters.md"}
+
+
+def counter_traffic(workload, kernel):
+    """Measured HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when
+    there is none for this workload or the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+
+    path = COUNTER_FILES.get(workload)
+    if not path or not os.path.exists(os.path.join(ROOT, path)):
+        return None
+    m = re.search(r"<!-- traffic-data (.*?) -->", open(os.path.join(ROOT, path)).read())
+    if not m:
+        return None
+    data = json.loads(m.group(1))
+    src = os.path.join(ROOT, "paper_2210_06014_amd", "csrc", "ft_kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != data.get("kernels_sha256"):
+        return None
+    return data["traffic_bytes_per_launch"].get(kernel)
+
+
 def copy_calibration(nbytes):
     """A plain copy kernel of known size: what FETCH_SIZE / WRITE_SIZE read for it calibrates the counters."""
     import torch
@@ -187,14 +209,17 @@ def main():
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
         t_s = kernels[dom]["ms_per_step"] / 1e3
         flops, byts = alg.get(dom, [0.0, 0.0])
+        traffic = counter_traffic(args.workload, dom) if args.nnz is None and not args.chunk else None
+        launches = kernels[dom]["launches_per_step"]
         if dom in ("factor_compose", "factor_apply"):
             ach = flops / t_s / 1e12
             roofline = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                        "frac": ach / PEAK_FP32_TFLOPS, "traffic": None}
+                        "frac": ach / PEAK_FP32_TFLOPS, "traffic": traffic,
+                        "algorithmic_per_launch": flops / launches, "algorithmic_bytes_per_launch": byts / launches}
         else:
             ach = byts / t_s / 1e9
             roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": ach / PEAK_HBM_GBS, "traffic": None}
+                        "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "algorithmic_per_launch": byts / launches}
         for k in kernels:
             if k in alg:
                 t_k = kernels[k]["ms_per_step"] / 1e3
