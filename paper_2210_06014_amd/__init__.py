@@ -21,3 +21,4 @@ from .api import (  # noqa: F401
     refresh,
     supported,
 )
+from .autograd import Reconstruction, reconstruct  # noqa: F401,E402
