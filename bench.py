@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--chunk", type=int, default=0, help="rows longer than this are split (0: library default)")
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16"],
+                    help="parameter storage: FP32, or BF16 copies with FP32 masters and accumulation")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -168,7 +170,7 @@ def main():
     t = time.time()
     plan = ft.Plan(w.dims, J, R, c, v, chunk=args.chunk)
     log(f"plan built and uploaded in {time.time() - t:.1f} s ({plan.device_bytes() / 2**30:.2f} GiB on device)")
-    prm = ft.Params(A, B)
+    prm = ft.Params(A, B, storage=args.storage)
     ft.refresh(plan, prm)
     rmse0 = float(ft.loss(plan, prm)[1].item())
     lossbuf = torch.empty(4, dtype=torch.float64, device="cuda")
@@ -209,7 +211,8 @@ def main():
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
         t_s = kernels[dom]["ms_per_step"] / 1e3
         flops, byts = alg.get(dom, [0.0, 0.0])
-        traffic = counter_traffic(args.workload, dom) if args.nnz is None and not args.chunk else None
+        traffic = (counter_traffic(args.workload, dom)
+                   if args.nnz is None and not args.chunk and args.storage == "f32" else None)
         launches = kernels[dom]["launches_per_step"]
         if dom in ("factor_compose", "factor_apply"):
             ach = flops / t_s / 1e12
@@ -244,7 +247,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.storage == "f32" else "bf16 storage, f32 arithmetic",
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {'x'.join(map(str, w.dims))}, {nnz} distinct coordinates, "

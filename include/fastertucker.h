@@ -67,11 +67,28 @@ typedef struct {
   int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM */
 } ft_desc;
 
-/* Device parameters of one model.  A[n], B[n], C[n] for n < order. */
+/* ft_params.storage */
+#define FT_STORE_F32 0  /* A, B, C are read and written in FP32 */
+#define FT_STORE_BF16 1 /* A16, B16, C16 are read; the FP32 masters A, B receive the updates */
+
+/*
+ * Device parameters of one model, for n < order.
+ *   FT_STORE_F32:  A[n] (I_n x J), B[n] (J x R), C[n] (I_n x R), FP32.
+ *   FT_STORE_BF16: the FP32 masters A[n], B[n] plus their BF16 copies
+ *                  A16[n], B16[n] and C16[n] = bf16(A16[n] B16[n]) (uint16_t
+ *                  arrays holding bfloat16 bits, same shapes); C[n] unused.
+ *                  Every kernel reads the BF16 arrays and accumulates in FP32;
+ *                  updates go to the masters, and each refresh rounds the
+ *                  masters to BF16 (nearest even) before forming C16.
+ */
 typedef struct {
   float* A[FT_MAX_ORDER];
   float* B[FT_MAX_ORDER];
   float* C[FT_MAX_ORDER];
+  void* A16[FT_MAX_ORDER];
+  void* B16[FT_MAX_ORDER];
+  void* C16[FT_MAX_ORDER];
+  int32_t storage;
 } ft_params;
 
 /* Host-side statistics of one mode of a plan (for diagnostics and tests). */

@@ -62,11 +62,19 @@ class FtDesc(ctypes.Structure):
     ]
 
 
+FT_STORE_F32 = 0
+FT_STORE_BF16 = 1
+
+
 class FtParams(ctypes.Structure):
     _fields_ = [
         ("A", ctypes.c_void_p * MAX_ORDER),
         ("B", ctypes.c_void_p * MAX_ORDER),
         ("C", ctypes.c_void_p * MAX_ORDER),
+        ("A16", ctypes.c_void_p * MAX_ORDER),
+        ("B16", ctypes.c_void_p * MAX_ORDER),
+        ("C16", ctypes.c_void_p * MAX_ORDER),
+        ("storage", ctypes.c_int32),
     ]
 
 

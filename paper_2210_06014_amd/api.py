@@ -110,14 +110,27 @@ class Plan:
 
 
 class Params:
-    """Device parameters: A(n) (I_n x J), B(n) (J x R), C(n) (I_n x R) as contiguous float32 CUDA tensors."""
+    """Device parameters as contiguous CUDA tensors.
 
-    def __init__(self, A, B, C=None, device="cuda"):
+    storage "f32": A(n) (I_n x J), B(n) (J x R), C(n) (I_n x R), float32.
+    storage "bf16": float32 masters A(n), B(n) plus bfloat16 copies A16, B16 and C16 (C is not used)."""
+
+    def __init__(self, A, B, C=None, device="cuda", storage="f32"):
         import torch
 
+        if storage not in ("f32", "bf16"):
+            raise ValueError("storage must be 'f32' or 'bf16'")
+        self.storage = storage
         self.A = [torch.as_tensor(a, dtype=torch.float32).to(device).contiguous() for a in A]
         self.B = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for b in B]
-        if C is None:
+        self.A16 = self.B16 = self.C16 = None
+        if storage == "bf16":
+            self.A16 = [torch.empty(a.shape, dtype=torch.bfloat16, device=device) for a in self.A]
+            self.B16 = [torch.empty(b.shape, dtype=torch.bfloat16, device=device) for b in self.B]
+            self.C16 = [torch.empty((a.shape[0], b.shape[1]), dtype=torch.bfloat16, device=device)
+                        for a, b in zip(self.A, self.B)]
+            self.C = [None] * len(self.A)
+        elif C is None:
             self.C = [torch.empty((a.shape[0], b.shape[1]), dtype=torch.float32, device=device)
                       for a, b in zip(self.A, self.B)]
         else:
@@ -127,18 +140,35 @@ class Params:
     @property
     def struct(self) -> FtParams:
         s = FtParams()
-        for n, (a, b, c) in enumerate(zip(self.A, self.B, self.C)):
-            for t in (a, b, c):
-                if not (t.is_cuda and t.dtype.is_floating_point and t.is_contiguous()):
-                    raise ValueError("parameters must be contiguous CUDA float32 tensors")
-            s.A[n] = a.data_ptr()
-            s.B[n] = b.data_ptr()
-            s.C[n] = c.data_ptr()
+        s.storage = _lib.FT_STORE_BF16 if self.storage == "bf16" else _lib.FT_STORE_F32
+        for n in range(len(self.A)):
+            ts = [self.A[n], self.B[n]] + ([self.C[n]] if self.storage == "f32" else
+                                          [self.A16[n], self.B16[n], self.C16[n]])
+            for t in ts:
+                if not (t.is_cuda and t.is_contiguous()):
+                    raise ValueError("parameters must be contiguous CUDA tensors")
+            s.A[n] = self.A[n].data_ptr()
+            s.B[n] = self.B[n].data_ptr()
+            if self.storage == "f32":
+                s.C[n] = self.C[n].data_ptr()
+            else:
+                s.A16[n] = self.A16[n].data_ptr()
+                s.B16[n] = self.B16[n].data_ptr()
+                s.C16[n] = self.C16[n].data_ptr()
         self._struct = s
         return s
 
     def clone(self) -> "Params":
-        return Params([a.clone() for a in self.A], [b.clone() for b in self.B], [c.clone() for c in self.C])
+        p = Params.__new__(Params)
+        p.storage = self.storage
+        p.A = [a.clone() for a in self.A]
+        p.B = [b.clone() for b in self.B]
+        p.C = [None if c is None else c.clone() for c in self.C]
+        p.A16 = None if self.A16 is None else [t.clone() for t in self.A16]
+        p.B16 = None if self.B16 is None else [t.clone() for t in self.B16]
+        p.C16 = None if self.C16 is None else [t.clone() for t in self.C16]
+        p._struct = None
+        return p
 
 
 def _p(params: Params):

@@ -14,27 +14,23 @@ import torch
 from . import api
 
 
-def _params(plan, A, B):
-    C = [torch.empty((a.shape[0], plan.R), dtype=torch.float32, device=a.device) for a in A]
-    p = api.Params.__new__(api.Params)
-    p.A = [a.detach().contiguous() for a in A]
-    p.B = [b.detach().contiguous() for b in B]
-    p.C = C
-    p._struct = None
+def _params(plan, A, B, storage):
+    p = api.Params([a.detach() for a in A], [b.detach() for b in B], device=A[0].device, storage=storage)
     api.refresh(plan, p)
     return p
 
 
 class Reconstruction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, plan, *params):
+    def forward(ctx, plan, storage, *params):
         N = plan.order
         A, B = params[:N], params[N:]
         if len(B) != N:
             raise ValueError("expected A(0..N-1) then B(0..N-1)")
-        p = _params(plan, A, B)
+        p = _params(plan, A, B, storage)
         out = api.forward(plan, p)
         ctx.plan = plan
+        ctx.storage = storage
         ctx.save_for_backward(*A, *B)
         return out
 
@@ -43,11 +39,14 @@ class Reconstruction(torch.autograd.Function):
         plan = ctx.plan
         N = plan.order
         saved = ctx.saved_tensors
-        p = _params(plan, saved[:N], saved[N:])
+        p = _params(plan, saved[:N], saved[N:], ctx.storage)
         gA, gB = api.grad(plan, p, grad_out.contiguous())
-        return (None, *gA, *gB)
+        return (None, None, *gA, *gB)
 
 
-def reconstruct(plan, A, B):
-    """xhat (input order) as a differentiable function of the lists A and B; the plan needs with_perm=True."""
-    return Reconstruction.apply(plan, *A, *B)
+def reconstruct(plan, A, B, storage="f32"):
+    """xhat (input order) as a differentiable function of the lists A and B; the plan needs with_perm=True.
+
+    storage "bf16" evaluates forward and backward on BF16 copies of A, B, C with FP32 accumulation;
+    the gradients are FP32 tensors for the FP32 leaves A, B."""
+    return Reconstruction.apply(plan, storage, *A, *B)

@@ -9,6 +9,7 @@
 //    per element, each lane gathering a 16-byte slice of every C(n) row;
 //  * C refresh: v_mfma_f32_16x16x4_f32 tiles of 16 rows.
 // No floating-point atomics: every reduction runs in a fixed order.
+#include <algorithm>
 #include <type_traits>
 
 #include "ft_internal.h"
@@ -110,10 +111,27 @@ __device__ __forceinline__ void axpy_bcast(float* v, float src, float t) {
   if constexpr (K == 16) axpy_bcast16(v, src, t); else axpy_bcast8(v, src, t);
 }
 
-template <int N>
+// Parameter storage: float (FP32) or uint16_t holding BF16 bits.  BF16 is
+// widened exactly by a 16-bit shift; all arithmetic is FP32.
+__device__ __forceinline__ float to_f(float x) { return x; }
+__device__ __forceinline__ float to_f(uint16_t x) { return __uint_as_float((uint32_t)x << 16); }
+
+template <int N, class T = float>
 struct CPtrs {
-  const float* p[N > 1 ? N - 1 : 1];
+  const T* p[N > 1 ? N - 1 : 1];
 };
+
+// four consecutive values starting at p (16-byte aligned for float, 8-byte for BF16)
+__device__ __forceinline__ floatx4 load4(const float* p) { return *reinterpret_cast<const floatx4*>(p); }
+__device__ __forceinline__ floatx4 load4(const uint16_t* p) {
+  const uint2 u = *reinterpret_cast<const uint2*>(p);
+  floatx4 r;
+  r[0] = __uint_as_float(u.x << 16);
+  r[1] = __uint_as_float(u.x & 0xFFFF0000u);
+  r[2] = __uint_as_float(u.y << 16);
+  r[3] = __uint_as_float(u.y & 0xFFFF0000u);
+  return r;
+}
 
 // ---------------------------------------------------------------------------
 // C = A B  (I x J) (J x R), FP32 MFMA 16x16x4.  One wavefront per 16 rows.
@@ -147,6 +165,57 @@ __global__ __launch_bounds__(256) void k_refresh(const float* __restrict__ A, co
   }
 }
 
+// BF16 storage: C16 = bf16(A16 B16) with v_mfma_f32_16x16x16_bf16 (FP32
+// accumulation).  Lane l supplies A[l%16][4(l/16) .. 4(l/16)+3] and
+// B[4(l/16) .. +3][l%16]; the result layout is that of the FP32 tile.
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  // round to nearest even on the upper 16 bits (IEEE-754 binary32 -> bfloat16); NaN stays NaN
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <int J, int R>
+__global__ __launch_bounds__(256) void k_refresh_bf16(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
+                                                      uint16_t* __restrict__ C, int64_t I) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (row0 >= I) return;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t ia = row0 + li;
+  constexpr int CT = (R + 15) / 16;
+  constexpr int KB = (J + 15) / 16;
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int col = ct * 16 + li;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      shortx4 a, b;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = kb * 16 + lk * 4 + u;
+        a[u] = (ia < I && k < J) ? (short)A[ia * J + k] : (short)0;
+        b[u] = (col < R && k < J) ? (short)B[k * R + col] : (short)0;
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = row0 + lk * 4 + v;
+      if (r < I && col < R) C[r * R + col] = f2bf(acc[v]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cast_bf16(const float* __restrict__ src, uint16_t* __restrict__ dst,
+                                                   int64_t n) {
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
+    dst[k] = f2bf(src[k]);
+}
+
 // ---------------------------------------------------------------------------
 // Factor pass.  Each element x of a row, in order:
 //     w = prod_{n != m} C(n)[i_n, :],  g = B(m) w,  e = x - a.g,
@@ -159,8 +228,8 @@ __global__ __launch_bounds__(256) void k_refresh(const float* __restrict__ A, co
 // Steps past the end of an item use w = 0 and no decay, which leaves every
 // state unchanged, so the wavefront needs no divergent control flow.
 
-template <int N, int R>
-__device__ __forceinline__ void gather_w(const CPtrs<N>& cp, const int (&ix)[N > 1 ? N - 1 : 1], int l, int t0,
+template <int N, int R, class T>
+__device__ __forceinline__ void gather_w(const CPtrs<N, T>& cp, const int (&ix)[N > 1 ? N - 1 : 1], int l, int t0,
                                          int len, float (&w)[16][R >= 16 ? R / 16 : 1]) {
   constexpr int RE = R >= 16 ? R / 16 : 1;
   static_for<0, 16>([&](auto S) {
@@ -172,9 +241,9 @@ __device__ __forceinline__ void gather_w(const CPtrs<N>& cp, const int (&ix)[N >
 #pragma unroll
     for (int q = 0; q < RE; ++q) {
       const int r = R >= 16 ? l + 16 * q : (l % R);
-      float prod = cp.p[0][(int64_t)ii[0] * R + r];
+      float prod = to_f(cp.p[0][(int64_t)ii[0] * R + r]);
 #pragma unroll
-      for (int k = 1; k < N - 1; ++k) prod *= cp.p[k][(int64_t)ii[k] * R + r];
+      for (int k = 1; k < N - 1; ++k) prod *= to_f(cp.p[k][(int64_t)ii[k] * R + r]);
       w[s][q] = sv ? prod : 0.f;
     }
   });
@@ -195,11 +264,11 @@ __device__ __forceinline__ void shared_g(const float (&Bw)[J >= 16 ? J / 16 : 1]
   }
 }
 
-template <int N, int J, int R>
+template <int N, int J, int R, class T>
 __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ items, int64_t n_items,
                                                       const int32_t* __restrict__ idx, int64_t nnz,
-                                                      const float* __restrict__ val, CPtrs<N> cp,
-                                                      const float* __restrict__ Bm, float* __restrict__ Am,
+                                                      const float* __restrict__ val, CPtrs<N, T> cp,
+                                                      const T* __restrict__ Bm, float* __restrict__ Am,
                                                       float* __restrict__ hvec, float lr, float c1) {
   constexpr int E = J >= 16 ? J / 16 : 1;
   constexpr int RE = R >= 16 ? R / 16 : 1;
@@ -212,7 +281,7 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
   for (int e = 0; e < E; ++e) {
     const int j = l + 16 * e;
 #pragma unroll
-    for (int r = 0; r < R; ++r) Bw[e][r] = j < J ? Bm[j * R + r] : 0.f;
+    for (int r = 0; r < R; ++r) Bw[e][r] = j < J ? to_f(Bm[j * R + r]) : 0.f;
   }
   // The row is carried in FP64 registers and rounded to FP32 once when
   // stored: the decay step lr*lam*a is about a hundred ulps of a, nearly the
@@ -236,7 +305,7 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
     for (int k = 0; k < N - 1; ++k) ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] : 0;
     const float xv = it.len > 0 ? val[p] : 0.f;
     float w[16][RE];
-    gather_w<N, R>(cp, ix, l, t0, it.len, w);
+    gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
     static_for<0, 16>([&](auto S) {
       constexpr int s = decltype(S)::value;
       float g[E];
@@ -275,11 +344,11 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
 //     Nm <- Nm - gp g (g + Nm^T g)^T     (Nm = prod (I - gp g g^T) - I)
 //     v  <- v + (-lr lam) v + lr (x - v.g) g
 // (v is the state reached from a = 0).  Lane j keeps column j of Nm.
-template <int N, int J, int R>
+template <int N, int J, int R, class T>
 __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict__ items, int64_t n_items,
                                                         const int32_t* __restrict__ idx, int64_t nnz,
-                                                        const float* __restrict__ val, CPtrs<N> cp,
-                                                        const float* __restrict__ Bm, float* __restrict__ maps,
+                                                        const float* __restrict__ val, CPtrs<N, T> cp,
+                                                        const T* __restrict__ Bm, float* __restrict__ maps,
                                                         int64_t* __restrict__ map_cnt, float lr, float c1, float gp) {
   constexpr int E = J >= 16 ? J / 16 : 1;
   constexpr int RE = R >= 16 ? R / 16 : 1;
@@ -293,7 +362,7 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
   for (int e = 0; e < E; ++e) {
     const int j = l + 16 * e;
 #pragma unroll
-    for (int r = 0; r < R; ++r) Bw[e][r] = j < J ? Bm[j * R + r] : 0.f;
+    for (int r = 0; r < R; ++r) Bw[e][r] = j < J ? to_f(Bm[j * R + r]) : 0.f;
   }
   float Nc[E][J];
   float v[E];
@@ -315,7 +384,7 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
     for (int k = 0; k < N - 1; ++k) ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] : 0;
     const float xv = it.len > 0 ? val[p] : 0.f;
     float w[16][RE];
-    gather_w<N, R>(cp, ix, l, t0, it.len, w);
+    gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
     static_for<0, 16>([&](auto S) {
       constexpr int s = decltype(S)::value;
       float g[E];
@@ -448,23 +517,23 @@ constexpr int kUnroll = 4;
 // prod over the gathered 16-byte slices of C rows.  Invalid slots carry index
 // 0 (a valid row) and are zeroed after the loads, so that the loads need no
 // branch and all of them can be in flight together.
-template <int N, int R>
-__device__ __forceinline__ floatx4 gather_row_product(const CPtrs<N>& cp, const int32_t (&ik)[N > 1 ? N - 1 : 1],
+template <int N, int R, class T>
+__device__ __forceinline__ floatx4 gather_row_product(const CPtrs<N, T>& cp, const int32_t (&ik)[N > 1 ? N - 1 : 1],
                                                       bool vld, int q) {
-  floatx4 w = *reinterpret_cast<const floatx4*>(cp.p[0] + (int64_t)ik[0] * R + 4 * q);
+  floatx4 w = load4(cp.p[0] + (int64_t)ik[0] * R + 4 * q);
 #pragma unroll
-  for (int k = 1; k < N - 1; ++k) w *= *reinterpret_cast<const floatx4*>(cp.p[k] + (int64_t)ik[k] * R + 4 * q);
+  for (int k = 1; k < N - 1; ++k) w *= load4(cp.p[k] + (int64_t)ik[k] * R + 4 * q);
   const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
   return vld ? w : zero;
 }
 
 // MODE 0: s = sum e w (core gradient); MODE 1: t = sum -e w (gradient of 1/2 sum e^2);
 // MODE 2: t = sum delta w with delta from the caller (input order, via perm).
-template <int N, int J, int R, int MODE>
+template <int N, int J, int R, int MODE, class T>
 __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, int64_t nseg,
                                                 const int32_t* __restrict__ idx, int64_t nnz,
-                                                const float* __restrict__ val, CPtrs<N> cp,
-                                                const float* __restrict__ Cm, const float* __restrict__ Am,
+                                                const float* __restrict__ val, CPtrs<N, T> cp,
+                                                const T* __restrict__ Cm, const T* __restrict__ Am,
                                                 const float* __restrict__ up, const int32_t* __restrict__ perm,
                                                 float* __restrict__ partials, float* __restrict__ tseg) {
   constexpr int QL = R / 4;
@@ -482,7 +551,7 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
   for (int64_t sg = (int64_t)blockIdx.x * 4 + wave; sg < nseg; sg += nw) {
     const Seg S = segs[sg];
     floatx4 crow = {0.f, 0.f, 0.f, 0.f};
-    if (MODE != 2) crow = *reinterpret_cast<const floatx4*>(Cm + (int64_t)S.row * R + 4 * q);
+    if (MODE != 2) crow = load4(Cm + (int64_t)S.row * R + 4 * q);
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     // U element groups per trip: all index loads, then all gathers, then the
     // arithmetic, so that each wavefront keeps U times more loads in flight.
@@ -506,7 +575,7 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
       }
       floatx4 w[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) w[u] = gather_row_product<N, R>(cp, ik[u], vl[u], q);
+      for (int u = 0; u < kUnroll; ++u) w[u] = gather_row_product<N, R, T>(cp, ik[u], vl[u], q);
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         float d;
@@ -535,7 +604,7 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
     for (int u = 0; u < GJ; ++u) {
       const int j = slot + P * u;
       if (j < J) {
-        const float aj = Am[(int64_t)S.row * J + j];
+        const float aj = to_f(Am[(int64_t)S.row * J + j]);
 #pragma unroll
         for (int c = 0; c < 4; ++c) Gp[u][c] = fmaf(aj, acc[c], Gp[u][c]);
       }
@@ -584,9 +653,9 @@ __global__ __launch_bounds__(256) void k_reduce_update(const float* __restrict__
 }
 
 // dA(m)[i, j] = sum_r B(m)[j, r] t_i[r], t_i = sum of the row's segment sums.
-template <int J, int R>
+template <int J, int R, class T>
 __global__ __launch_bounds__(256) void k_grad_rows(const int64_t* __restrict__ seg_ptr, const float* __restrict__ tseg,
-                                                   const float* __restrict__ Bm, float* __restrict__ gA, int64_t I) {
+                                                   const T* __restrict__ Bm, float* __restrict__ gA, int64_t I) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= I * J) return;
   const int64_t i = e / J;
@@ -599,17 +668,17 @@ __global__ __launch_bounds__(256) void k_grad_rows(const int64_t* __restrict__ s
     for (int r = 0; r < R; ++r) t[r] += tseg[sg * R + r];
   float s = 0.f;
 #pragma unroll
-  for (int r = 0; r < R; ++r) s = fmaf(Bm[j * R + r], t[r], s);
+  for (int r = 0; r < R; ++r) s = fmaf(to_f(Bm[j * R + r]), t[r], s);
   gA[e] = s;
 }
 
 // Loss: per-element e^2 summed in FP64 (and, with out != nullptr, xhat stored
 // at the element's input position).
-template <int N, int R>
+template <int N, int R, class T>
 __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int64_t nseg,
                                               const int32_t* __restrict__ idx, int64_t nnz,
-                                              const float* __restrict__ val, CPtrs<N> cp,
-                                              const float* __restrict__ Cm, double* __restrict__ dpart,
+                                              const float* __restrict__ val, CPtrs<N, T> cp,
+                                              const T* __restrict__ Cm, double* __restrict__ dpart,
                                               const int32_t* __restrict__ perm, float* __restrict__ out) {
   constexpr int QL = R / 4;
   constexpr int P = 64 / QL;
@@ -620,7 +689,7 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
   double sse = 0.0;
   for (int64_t sg = (int64_t)blockIdx.x * 4 + wave; sg < nseg; sg += nw) {
     const Seg S = segs[sg];
-    const floatx4 crow = *reinterpret_cast<const floatx4*>(Cm + (int64_t)S.row * R + 4 * q);
+    const floatx4 crow = load4(Cm + (int64_t)S.row * R + 4 * q);
     for (int t0 = 0; t0 < S.len; t0 += P * kUnroll) {
       bool vl[kUnroll];
       int64_t pp[kUnroll];
@@ -636,7 +705,7 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
       }
       floatx4 w[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) w[u] = gather_row_product<N, R>(cp, ik[u], vl[u], q);
+      for (int u = 0; u < kUnroll; ++u) w[u] = gather_row_product<N, R, T>(cp, ik[u], vl[u], q);
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         float xh = crow[0] * w[u][0];
@@ -706,9 +775,9 @@ __global__ __launch_bounds__(256) void k_loss_finish(const double* __restrict__ 
 }
 
 // Predictions for query coordinates (structure of arrays [N][q]).
-template <int N, int R>
+template <int N, int R, class T>
 __global__ __launch_bounds__(256) void k_predict(const int32_t* __restrict__ coords, int64_t q,
-                                                 CPtrs<N + 1> cp, float* __restrict__ out) {
+                                                 CPtrs<N + 1, T> cp, float* __restrict__ out) {
   constexpr int QL = R / 4;
   const int64_t tid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t x = tid / QL;
@@ -718,7 +787,7 @@ __global__ __launch_bounds__(256) void k_predict(const int32_t* __restrict__ coo
 #pragma unroll
   for (int n = 0; n < N; ++n) {
     const int32_t i = vld ? coords[(int64_t)n * q + x] : 0;
-    const floatx4 c = *reinterpret_cast<const floatx4*>(cp.p[n] + (int64_t)i * R + 4 * qq);
+    const floatx4 c = load4(cp.p[n] + (int64_t)i * R + 4 * qq);
     w *= c;
   }
   float s = ((w[0] + w[1]) + w[2]) + w[3];
@@ -733,29 +802,47 @@ __global__ __launch_bounds__(256) void k_predict(const int32_t* __restrict__ coo
 
 constexpr int key(int N, int J, int R) { return (N * 64 + J) * 64 + R; }
 
-template <int N>
-CPtrs<N> others(const ft_params* p, int m) {
-  CPtrs<N> c{};
-  for (int k = 0; k < N - 1; ++k) c.p[k] = p->C[(m + 1 + k) % N];
+// Typed views of the parameter set: FP32 storage reads A, B, C; BF16 storage
+// reads the BF16 copies A16, B16, C16 (the FP32 masters A, B take the updates).
+template <class T>
+struct Store;
+template <>
+struct Store<float> {
+  static const float* A(const ft_params* p, int n) { return p->A[n]; }
+  static const float* B(const ft_params* p, int n) { return p->B[n]; }
+  static const float* C(const ft_params* p, int n) { return p->C[n]; }
+};
+template <>
+struct Store<uint16_t> {
+  static const uint16_t* A(const ft_params* p, int n) { return (const uint16_t*)p->A16[n]; }
+  static const uint16_t* B(const ft_params* p, int n) { return (const uint16_t*)p->B16[n]; }
+  static const uint16_t* C(const ft_params* p, int n) { return (const uint16_t*)p->C16[n]; }
+};
+
+template <int N, class T>
+CPtrs<N, T> others(const ft_params* p, int m) {
+  CPtrs<N, T> c{};
+  for (int k = 0; k < N - 1; ++k) c.p[k] = Store<T>::C(p, (m + 1 + k) % N);
   return c;
 }
 
-template <int N, int J, int R>
+template <int N, int J, int R, class T>
 hipError_t factor_impl(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
   const ModeMeta& M = P->meta[m];
   const ModeDev& D = P->dev[m];
-  const CPtrs<N> cp = others<N>(p, m);
+  const CPtrs<N, T> cp = others<N, T>(p, m);
+  const T* Bm = Store<T>::B(p, m);
   const double rho = 1.0 - lr * lam;
   const float flr = (float)lr, c1 = (float)(-lr * lam), gp = (float)(lr / rho);
   if (M.n_compose > 0) {
     KTimer tm(P, FT_K_FACTOR_COMPOSE, s);
-    hipLaunchKernelGGL((k_factor_compose<N, J, R>), dim3((unsigned)((M.n_compose + 15) / 16)), dim3(256), 0, s,
-                       D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, p->B[m], P->maps, P->map_cnt, flr, c1, gp);
+    hipLaunchKernelGGL((k_factor_compose<N, J, R, T>), dim3((unsigned)((M.n_compose + 15) / 16)), dim3(256), 0, s,
+                       D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm, P->maps, P->map_cnt, flr, c1, gp);
   }
   if (M.n_apply > 0) {
     KTimer tm(P, FT_K_FACTOR_APPLY, s);
-    hipLaunchKernelGGL((k_factor_apply<N, J, R>), dim3((unsigned)((M.n_apply + 15) / 16)), dim3(256), 0, s, D.apply,
-                       M.n_apply, D.idx, P->nnz, D.val, cp, p->B[m], p->A[m], P->hvec, flr, c1);
+    hipLaunchKernelGGL((k_factor_apply<N, J, R, T>), dim3((unsigned)((M.n_apply + 15) / 16)), dim3(256), 0, s,
+                       D.apply, M.n_apply, D.idx, P->nnz, D.val, cp, Bm, p->A[m], P->hvec, flr, c1);
   }
   for (size_t L = 0; L < M.level_len.size(); ++L) {
     KTimer tm(P, FT_K_COMBINE, s);
@@ -784,40 +871,43 @@ int seg_blocks(int64_t nseg) {
   return (int)b;
 }
 
-template <int N, int J, int R>
+template <int N, int J, int R, class T>
 hipError_t segsum_impl(const ft_plan* P, int m, const ft_params* p, int mode, const float* up, float* tseg,
                        hipStream_t s, int* nblocks) {
   const ModeMeta& M = P->meta[m];
   const ModeDev& D = P->dev[m];
-  const CPtrs<N> cp = others<N>(p, m);
+  const CPtrs<N, T> cp = others<N, T>(p, m);
+  const T* Cm = Store<T>::C(p, m);
+  const T* Am = Store<T>::A(p, m);
   const int nb = seg_blocks(M.n_segs);
   *nblocks = nb;
   KTimer tm(P, FT_K_SEGSUM, s);
   if (mode == 0)
-    hipLaunchKernelGGL((k_segsum<N, J, R, 0>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp,
-                       p->C[m], p->A[m], nullptr, nullptr, P->partials, tseg);
+    hipLaunchKernelGGL((k_segsum<N, J, R, 0, T>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val,
+                       cp, Cm, Am, nullptr, nullptr, P->partials, tseg);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_segsum<N, J, R, 1>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp,
-                       p->C[m], p->A[m], nullptr, nullptr, P->partials, tseg);
+    hipLaunchKernelGGL((k_segsum<N, J, R, 1, T>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val,
+                       cp, Cm, Am, nullptr, nullptr, P->partials, tseg);
   else
-    hipLaunchKernelGGL((k_segsum<N, J, R, 2>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp,
-                       p->C[m], p->A[m], up, D.perm, P->partials, tseg);
+    hipLaunchKernelGGL((k_segsum<N, J, R, 2, T>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val,
+                       cp, Cm, Am, up, D.perm, P->partials, tseg);
   return hipGetLastError();
 }
 
-template <int N, int J, int R>
+template <int N, int J, int R, class T>
 hipError_t loss_impl(const ft_plan* P, const ft_params* p, double lam_a, double lam_b, double* out4, float* xout,
                      hipStream_t s) {
   const ModeMeta& M = P->meta[0];
   const ModeDev& D = P->dev[0];
-  const CPtrs<N> cp = others<N>(p, 0);
+  const CPtrs<N, T> cp = others<N, T>(p, 0);
   const int nb = seg_blocks(M.n_segs);
   {
     KTimer tm(P, FT_K_LOSS, s);
-    hipLaunchKernelGGL((k_loss<N, R>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp,
-                       p->C[0], out4 ? P->dpartials : nullptr, D.perm, xout);
+    hipLaunchKernelGGL((k_loss<N, R, T>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp,
+                       Store<T>::C(p, 0), out4 ? P->dpartials : nullptr, D.perm, xout);
   }
   if (!out4) return hipGetLastError();
+  // the regularisers of Eq. (6) are taken on the FP32 masters
   KTimer tm(P, FT_K_REDUCE, s);
   double* rpart = P->dpartials + kPartials;
   for (int n = 0; n < N; ++n)
@@ -831,15 +921,27 @@ hipError_t loss_impl(const ft_plan* P, const ft_params* p, double lam_a, double 
   return hipGetLastError();
 }
 
-template <int N, int R>
+template <int N, int R, class T>
 hipError_t predict_impl(const ft_params* p, const int32_t* coords, int64_t q, float* out, hipStream_t s) {
-  CPtrs<N + 1> cp{};
-  for (int n = 0; n < N; ++n) cp.p[n] = p->C[n];
+  CPtrs<N + 1, T> cp{};
+  for (int n = 0; n < N; ++n) cp.p[n] = Store<T>::C(p, n);
   const int64_t threads = q * (R / 4);
   const unsigned nb = (unsigned)((threads + 255) / 256);
-  if (nb > 0) hipLaunchKernelGGL((k_predict<N, R>), dim3(nb), dim3(256), 0, s, coords, q, cp, out);
+  if (nb > 0) hipLaunchKernelGGL((k_predict<N, R, T>), dim3(nb), dim3(256), 0, s, coords, q, cp, out);
   return hipGetLastError();
 }
+
+template <int J, int R, class T>
+hipError_t grad_rows_impl(const ft_plan* P, int m, const ft_params* p, float* gA, hipStream_t s) {
+  const int64_t I = P->desc.dims[m];
+  const unsigned gb = (unsigned)((I * J + 255) / 256);
+  if (gb > 0)
+    hipLaunchKernelGGL((k_grad_rows<J, R, T>), dim3(gb), dim3(256), 0, s, P->dev[m].seg_ptr, P->tseg,
+                       Store<T>::B(p, m), gA, I);
+  return hipGetLastError();
+}
+
+bool bf16(const ft_params* p) { return p->storage == FT_STORE_BF16; }
 
 }  // namespace
 
@@ -855,16 +957,32 @@ bool supported(int N, int J, int R) {
 
 hipError_t launch_refresh(const ft_plan* P, int n, const ft_params* p, hipStream_t s) {
   const int64_t I = P->desc.dims[n];
-  const float* A = p->A[n];
-  const float* B = p->B[n];
-  float* C = p->C[n];
   const unsigned nb = (unsigned)(((I + 15) / 16 + 3) / 4);
-  if (nb == 0) return hipSuccess;
   KTimer tm(P, FT_K_REFRESH, s);
+  if (bf16(p)) {
+    // BF16 copies of the masters (round to nearest even), then C16 = bf16(A16 B16)
+    const int64_t na = I * P->J, nbm = (int64_t)P->J * P->R;
+    hipLaunchKernelGGL(k_cast_bf16, dim3((unsigned)std::min<int64_t>((na + 255) / 256, 4096) + (na == 0)), dim3(256),
+                       0, s, p->A[n], (uint16_t*)p->A16[n], na);
+    hipLaunchKernelGGL(k_cast_bf16, dim3((unsigned)((nbm + 255) / 256)), dim3(256), 0, s, p->B[n],
+                       (uint16_t*)p->B16[n], nbm);
+    if (nb == 0) return hipGetLastError();
+    switch (P->J * 64 + P->R) {
+#define X(n_, j, r)                                                                                       \
+  case j * 64 + r:                                                                                        \
+    hipLaunchKernelGGL((k_refresh_bf16<j, r>), dim3(nb), dim3(256), 0, s, (const uint16_t*)p->A16[n],    \
+                       (const uint16_t*)p->B16[n], (uint16_t*)p->C16[n], I);                              \
+    return hipGetLastError();
+      X(0, 8, 8) X(0, 16, 16) X(0, 32, 32) X(0, 8, 16)
+#undef X
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (nb == 0) return hipSuccess;
   switch (P->J * 64 + P->R) {
-#define X(n, j, r)                                                                              \
-  case j * 64 + r:                                                                              \
-    hipLaunchKernelGGL((k_refresh<j, r>), dim3(nb), dim3(256), 0, s, A, B, C, I);               \
+#define X(n_, j, r)                                                                                           \
+  case j * 64 + r:                                                                                            \
+    hipLaunchKernelGGL((k_refresh<j, r>), dim3(nb), dim3(256), 0, s, p->A[n], p->B[n], p->C[n], I);          \
     return hipGetLastError();
     X(0, 8, 8) X(0, 16, 16) X(0, 32, 32) X(0, 8, 16)
 #undef X
@@ -872,25 +990,29 @@ hipError_t launch_refresh(const ft_plan* P, int n, const ft_params* p, hipStream
   }
 }
 
-hipError_t launch_factor(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
-  switch (key(P->N, P->J, P->R)) {
-#define X(n, j, r) \
-  case key(n, j, r): return factor_impl<n, j, r>(P, m, p, lr, lam, s);
-    FT_CONFIGS(X)
-#undef X
-    default: return hipErrorInvalidValue;
+#define FT_DISPATCH(CALL)                                            \
+  switch (key(P->N, P->J, P->R)) {                                   \
+    FT_CONFIGS(X)                                                    \
+    default: return hipErrorInvalidValue;                            \
   }
+
+hipError_t launch_factor(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
+#define X(n, j, r)                                                                             \
+  case key(n, j, r):                                                                           \
+    return bf16(p) ? factor_impl<n, j, r, uint16_t>(P, m, p, lr, lam, s)                      \
+                   : factor_impl<n, j, r, float>(P, m, p, lr, lam, s);
+  FT_DISPATCH()
+#undef X
 }
 
 static hipError_t segsum(const ft_plan* P, int m, const ft_params* p, int mode, const float* up, float* tseg,
                          hipStream_t s, int* nb) {
-  switch (key(P->N, P->J, P->R)) {
-#define X(n, j, r) \
-  case key(n, j, r): return segsum_impl<n, j, r>(P, m, p, mode, up, tseg, s, nb);
-    FT_CONFIGS(X)
+#define X(n, j, r)                                                                             \
+  case key(n, j, r):                                                                           \
+    return bf16(p) ? segsum_impl<n, j, r, uint16_t>(P, m, p, mode, up, tseg, s, nb)           \
+                   : segsum_impl<n, j, r, float>(P, m, p, mode, up, tseg, s, nb);
+  FT_DISPATCH()
 #undef X
-    default: return hipErrorInvalidValue;
-  }
 }
 
 hipError_t launch_core_grad(const ft_plan* P, int m, const ft_params* p, hipStream_t s) {
@@ -910,34 +1032,31 @@ hipError_t launch_core_update(const ft_plan* P, int m, const ft_params* p, doubl
 }
 
 hipError_t launch_loss(const ft_plan* P, const ft_params* p, double lam_a, double lam_b, double* out4, hipStream_t s) {
-  switch (key(P->N, P->J, P->R)) {
-#define X(n, j, r) \
-  case key(n, j, r): return loss_impl<n, j, r>(P, p, lam_a, lam_b, out4, nullptr, s);
-    FT_CONFIGS(X)
+#define X(n, j, r)                                                                             \
+  case key(n, j, r):                                                                           \
+    return bf16(p) ? loss_impl<n, j, r, uint16_t>(P, p, lam_a, lam_b, out4, nullptr, s)       \
+                   : loss_impl<n, j, r, float>(P, p, lam_a, lam_b, out4, nullptr, s);
+  FT_DISPATCH()
 #undef X
-    default: return hipErrorInvalidValue;
-  }
 }
 
 hipError_t launch_forward(const ft_plan* P, const ft_params* p, float* out, hipStream_t s) {
-  switch (key(P->N, P->J, P->R)) {
-#define X(n, j, r) \
-  case key(n, j, r): return loss_impl<n, j, r>(P, p, 0.0, 0.0, nullptr, out, s);
-    FT_CONFIGS(X)
+#define X(n, j, r)                                                                             \
+  case key(n, j, r):                                                                           \
+    return bf16(p) ? loss_impl<n, j, r, uint16_t>(P, p, 0.0, 0.0, nullptr, out, s)            \
+                   : loss_impl<n, j, r, float>(P, p, 0.0, 0.0, nullptr, out, s);
+  FT_DISPATCH()
 #undef X
-    default: return hipErrorInvalidValue;
-  }
 }
 
 hipError_t launch_predict(const ft_plan* P, const ft_params* p, const int32_t* coords, int64_t q, float* out,
                           hipStream_t s) {
-  switch (key(P->N, P->J, P->R)) {
-#define X(n, j, r) \
-  case key(n, j, r): return predict_impl<n, r>(p, coords, q, out, s);
-    FT_CONFIGS(X)
+#define X(n, j, r)                                                                             \
+  case key(n, j, r):                                                                           \
+    return bf16(p) ? predict_impl<n, r, uint16_t>(p, coords, q, out, s)                       \
+                   : predict_impl<n, r, float>(p, coords, q, out, s);
+  FT_DISPATCH()
 #undef X
-    default: return hipErrorInvalidValue;
-  }
 }
 
 hipError_t launch_grad(const ft_plan* P, const ft_params* p, const float* up, float* const* gA, float* const* gB,
@@ -946,18 +1065,16 @@ hipError_t launch_grad(const ft_plan* P, const ft_params* p, const float* up, fl
     int nb = 0;
     hipError_t e = segsum(P, m, p, up ? 2 : 1, up, P->tseg, s, &nb);
     if (e != hipSuccess) return e;
-    const int64_t I = P->desc.dims[m];
-    const unsigned gb = (unsigned)((I * P->J + 255) / 256);
     switch (P->J * 64 + P->R) {
-#define X(n, j, r)                                                                                               \
-  case j * 64 + r:                                                                                               \
-    hipLaunchKernelGGL((k_grad_rows<j, r>), dim3(gb), dim3(256), 0, s, P->dev[m].seg_ptr, P->tseg, p->B[m], gA[m], \
-                       I);                                                                                       \
+#define X(n_, j, r)                                                                                        \
+  case j * 64 + r:                                                                                         \
+    e = bf16(p) ? grad_rows_impl<j, r, uint16_t>(P, m, p, gA[m], s) : grad_rows_impl<j, r, float>(P, m, p, gA[m], s); \
     break;
       X(0, 8, 8) X(0, 16, 16) X(0, 32, 32) X(0, 8, 16)
 #undef X
       default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess) return e;
     e = reduce_partials(P, nb, nullptr, gB[m], 0.f, 0.f, 0.f, 0, s);
     if (e != hipSuccess) return e;
   }

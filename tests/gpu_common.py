@@ -14,11 +14,11 @@ def make_problem(dims, nnz, zipf, J, R, seed, sigma=0.1, values="int1to5"):
     return c, v, A, B
 
 
-def gpu_setup(dims, J, R, c, v, A, B, **plan_kw):
+def gpu_setup(dims, J, R, c, v, A, B, storage="f32", **plan_kw):
     import paper_2210_06014_amd as ft
 
     plan = ft.Plan(dims, J, R, c, v, **plan_kw)
-    prm = ft.Params(A, B)
+    prm = ft.Params(A, B, storage=storage)
     ft.refresh(plan, prm)
     return plan, prm
 
@@ -47,3 +47,13 @@ def delta_ok(after_gpu, after_orc, before, rel=1e-3, abs_rel=1e-6):
     err = np.linalg.norm(after_gpu - after_orc)
     bound = rel * d + abs_rel * np.linalg.norm(after_orc)
     return err <= bound, err, bound
+
+
+def bf16_scale(A, B, coords):
+    """sum_r prod_n S(n)[i_n, r] with S(n) = |A(n)| |B(n)|: the scale of BF16 rounding errors in xhat."""
+    p = None
+    for n in range(len(A)):
+        S = np.abs(A[n].astype(np.float64)) @ np.abs(B[n].astype(np.float64))
+        rows = S[coords[n]]
+        p = rows if p is None else p * rows
+    return p.sum(axis=1)
