@@ -228,22 +228,30 @@ __global__ __launch_bounds__(256) void k_cast_bf16(const float* __restrict__ src
 // Steps past the end of an item use w = 0 and no decay, which leaves every
 // state unchanged, so the wavefront needs no divergent control flow.
 
+// value at byte offset `off` of a C table (uniform base + 32-bit offset: the
+// scalar-base addressing form; every table is far below 4 GB)
+template <class T>
+__device__ __forceinline__ float at_byte(const T* base, uint32_t off) {
+  return to_f(*reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off));
+}
+
+// ixb[k]: byte offset of element (lane t)'s row in the k-th other C table
 template <int N, int R, class T>
-__device__ __forceinline__ void gather_w(const CPtrs<N, T>& cp, const int (&ix)[N > 1 ? N - 1 : 1], int l, int t0,
+__device__ __forceinline__ void gather_w(const CPtrs<N, T>& cp, const int (&ixb)[N > 1 ? N - 1 : 1], int l, int t0,
                                          int len, float (&w)[16][R >= 16 ? R / 16 : 1]) {
   constexpr int RE = R >= 16 ? R / 16 : 1;
   static_for<0, 16>([&](auto S) {
     constexpr int s = decltype(S)::value;
-    int ii[N - 1];
+    uint32_t ib[N - 1];
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) ii[k] = bcast16i<s>(ix[k]);
+    for (int k = 0; k < N - 1; ++k) ib[k] = (uint32_t)bcast16i<s>(ixb[k]);
     const bool sv = (t0 + s) < len;
 #pragma unroll
     for (int q = 0; q < RE; ++q) {
-      const int r = R >= 16 ? l + 16 * q : (l % R);
-      float prod = to_f(cp.p[0][(int64_t)ii[0] * R + r]);
+      const uint32_t rb = (uint32_t)((R >= 16 ? l + 16 * q : (l % R)) * sizeof(T));
+      float prod = at_byte(cp.p[0], ib[0] + rb);
 #pragma unroll
-      for (int k = 1; k < N - 1; ++k) prod *= to_f(cp.p[k][(int64_t)ii[k] * R + r]);
+      for (int k = 1; k < N - 1; ++k) prod *= at_byte(cp.p[k], ib[k] + rb);
       w[s][q] = sv ? prod : 0.f;
     }
   });
@@ -302,7 +310,8 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
     const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
     int ix[N - 1];
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] : 0;
+    for (int k = 0; k < N - 1; ++k)
+      ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (int)(R * sizeof(T)) : 0;
     const float xv = it.len > 0 ? val[p] : 0.f;
     float w[16][RE];
     gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
@@ -381,7 +390,8 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
     const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
     int ix[N - 1];
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] : 0;
+    for (int k = 0; k < N - 1; ++k)
+      ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (int)(R * sizeof(T)) : 0;
     const float xv = it.len > 0 ? val[p] : 0.f;
     float w[16][RE];
     gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
@@ -520,9 +530,13 @@ constexpr int kUnroll = 4;
 template <int N, int R, class T>
 __device__ __forceinline__ floatx4 gather_row_product(const CPtrs<N, T>& cp, const int32_t (&ik)[N > 1 ? N - 1 : 1],
                                                       bool vld, int q) {
-  floatx4 w = load4(cp.p[0] + (int64_t)ik[0] * R + 4 * q);
+  const uint32_t qb = (uint32_t)(4 * q * sizeof(T));
+  floatx4 w = load4(reinterpret_cast<const T*>(reinterpret_cast<const char*>(cp.p[0]) +
+                                               ((uint32_t)ik[0] * (uint32_t)(R * sizeof(T)) + qb)));
 #pragma unroll
-  for (int k = 1; k < N - 1; ++k) w *= load4(cp.p[k] + (int64_t)ik[k] * R + 4 * q);
+  for (int k = 1; k < N - 1; ++k)
+    w *= load4(reinterpret_cast<const T*>(reinterpret_cast<const char*>(cp.p[k]) +
+                                          ((uint32_t)ik[k] * (uint32_t)(R * sizeof(T)) + qb)));
   const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
   return vld ? w : zero;
 }
@@ -540,7 +554,8 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
   constexpr int P = 64 / QL;
   constexpr int GJ = (J + P - 1) / P;
   __shared__ float red[4][J * R];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int slot = lane / QL, q = lane % QL;
   const int64_t nw = (int64_t)gridDim.x * 4;
   float Gp[GJ][4];
@@ -565,13 +580,14 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
         // positions past the end are clamped to the last element (a valid
         // address) so that the loads need no branch; their terms are zeroed
         vl[u] = (t0 + u * P + slot) < S.len;
-        pp[u] = S.start + min(t0 + u * P + slot, S.len - 1);
+        const uint32_t o = (uint32_t)min(t0 + u * P + slot, S.len - 1);
+        pp[u] = S.start + o;
 #pragma unroll
-        for (int k = 0; k < N - 1; ++k) ik[u][k] = idx[(int64_t)k * nnz + pp[u]];
+        for (int k = 0; k < N - 1; ++k) ik[u][k] = (idx + (int64_t)k * nnz + S.start)[o];
         if (MODE == 2)
-          xv[u] = up[perm[pp[u]]];
+          xv[u] = up[(perm + S.start)[o]];
         else
-          xv[u] = val[pp[u]];
+          xv[u] = (val + S.start)[o];
       }
       floatx4 w[kUnroll];
 #pragma unroll
@@ -683,7 +699,8 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
   constexpr int QL = R / 4;
   constexpr int P = 64 / QL;
   __shared__ double red[4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int slot = lane / QL, q = lane % QL;
   const int64_t nw = (int64_t)gridDim.x * 4;
   double sse = 0.0;
@@ -698,10 +715,11 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         vl[u] = (t0 + u * P + slot) < S.len;
-        pp[u] = S.start + min(t0 + u * P + slot, S.len - 1);
+        const uint32_t o = (uint32_t)min(t0 + u * P + slot, S.len - 1);
+        pp[u] = S.start + o;
 #pragma unroll
-        for (int k = 0; k < N - 1; ++k) ik[u][k] = idx[(int64_t)k * nnz + pp[u]];
-        xv[u] = val[pp[u]];
+        for (int k = 0; k < N - 1; ++k) ik[u][k] = (idx + (int64_t)k * nnz + S.start)[o];
+        xv[u] = (val + S.start)[o];
       }
       floatx4 w[kUnroll];
 #pragma unroll
