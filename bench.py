@@ -30,14 +30,19 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic(w, nnz, row_counts, chunk):
-    """Per-epoch algorithmic flops and bytes per kernel family (formulas in the design notes)."""
+def algorithmic(w, nnz, row_counts, chunk, fibers):
+    """Per-epoch algorithmic flops and bytes per kernel family (formulas in the design notes).
+
+    fibers[m] is the number of mode-m fibers when g = B(m) w is shared per fiber
+    (Section 3.2), else None: a shared mode computes g once per fiber and the
+    factor kernels read it instead of forming it per element.
+    """
     import numpy as np
 
     N, J, R = len(w.dims), w.J[0], w.R
-    f_elem = 2 * J * R + (N - 2) * R + 5 * J
     stream = (N - 1) * 4 + 4
-    out = {"factor_compose": [0.0, 0.0], "factor_apply": [0.0, 0.0], "segsum": [0.0, 0.0], "loss": [0.0, 0.0]}
+    out = {"factor_compose": [0.0, 0.0], "factor_apply": [0.0, 0.0], "fiber_g": [0.0, 0.0], "segsum": [0.0, 0.0],
+           "loss": [0.0, 0.0]}
     c_bytes = [d * R * 4 for d in w.dims]
     a_bytes = [d * J * 4 for d in w.dims]
     for m in range(N):
@@ -46,10 +51,23 @@ def algorithmic(w, nnz, row_counts, chunk):
         comp = float(np.sum(np.where(heavy, L - chunk, 0)))
         app = float(nnz - comp)
         others = sum(c_bytes) - c_bytes[m]
+        if fibers[m] is None:
+            f_elem = 2 * J * R + (N - 2) * R + 5 * J
+            e_bytes = stream
+            c_share = others
+        else:
+            # g per fiber: w (N-2 products of R), g = B w (2 J R); the factor
+            # kernels then stream the fiber id and read g (J floats).
+            nf = fibers[m]
+            out["fiber_g"][0] += nf * (2 * J * R + (N - 2) * R)
+            out["fiber_g"][1] += nf * ((N - 1) * 4 + J * 4) + others
+            f_elem = 5 * J
+            e_bytes = 4 + 4 + J * 4
+            c_share = 0.0
         out["factor_compose"][0] += comp * f_elem
-        out["factor_compose"][1] += comp * stream + others * comp / max(nnz, 1)
+        out["factor_compose"][1] += comp * e_bytes + c_share * comp / max(nnz, 1)
         out["factor_apply"][0] += app * f_elem
-        out["factor_apply"][1] += app * stream + others * app / max(nnz, 1) + 2 * a_bytes[m]
+        out["factor_apply"][1] += app * e_bytes + c_share * app / max(nnz, 1) + 2 * a_bytes[m]
         out["segsum"][0] += nnz * ((N - 2) * R + 4 * R) + w.dims[m] * 2 * J * R
         out["segsum"][1] += nnz * stream + others + c_bytes[m] + a_bytes[m]
     out["loss"][0] += nnz * (N * R + 3)
@@ -134,6 +152,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="rows longer than this are split (0: library default)")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16"],
                     help="parameter storage: FP32, or BF16 copies with FP32 masters and accumulation")
+    ap.add_argument("--no-fiber-share", action="store_true",
+                    help="form g = B(m) w per element instead of once per mode-m fiber (Section 3.2 ablation)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -168,7 +188,7 @@ def main():
     c, v, A, B = synth.make(w, nnz=nnz)
     log(f"generated in {time.time() - t:.1f} s")
     t = time.time()
-    plan = ft.Plan(w.dims, J, R, c, v, chunk=args.chunk)
+    plan = ft.Plan(w.dims, J, R, c, v, chunk=args.chunk, fiber_share=not args.no_fiber_share)
     log(f"plan built and uploaded in {time.time() - t:.1f} s ({plan.device_bytes() / 2**30:.2f} GiB on device)")
     prm = ft.Params(A, B, storage=args.storage)
     ft.refresh(plan, prm)
@@ -200,7 +220,9 @@ def main():
 
     value = 2 * N * nnz / (ms_step / 1e3)
     counts = [np.bincount(c[m], minlength=w.dims[m]) for m in range(N)]
-    alg = algorithmic(w, nnz, counts, args.chunk or 512)
+    infos = [plan.mode_info(m) for m in range(N)]
+    fibers = [info["fibers"] if info["fiber_shared"] else None for info in infos]
+    alg = algorithmic(w, nnz, counts, args.chunk or 512, fibers)
     kernels = {}
     for k, (ms, n) in prof.items():
         if n == 0:
@@ -212,7 +234,8 @@ def main():
         t_s = kernels[dom]["ms_per_step"] / 1e3
         flops, byts = alg.get(dom, [0.0, 0.0])
         traffic = (counter_traffic(args.workload, dom)
-                   if args.nnz is None and not args.chunk and args.storage == "f32" else None)
+                   if args.nnz is None and not args.chunk and args.storage == "f32" and not args.no_fiber_share
+                   else None)
         launches = kernels[dom]["launches_per_step"]
         if dom in ("factor_compose", "factor_apply"):
             ach = flops / t_s / 1e12
@@ -253,6 +276,8 @@ def main():
             "workload": f"{args.workload}: {'x'.join(map(str, w.dims))}, {nnz} distinct coordinates, "
             f"Zipf({w.zipf}) per mode, values {w.value_kind}, J={J}, R={R}, lr={w.lr}, lam={w.lam}, init N(0,{w.sigma}^2)",
             "step": "factor pass + C refresh per mode, core pass + C refresh per mode, RMSE pass",
+            "fiber_shared_modes": [m for m in range(N) if fibers[m] is not None],
+            "fibers_per_mode": [info["fibers"] for info in infos],
             "rmse_start": rmse0,
             "rmse_end": rmse,
         },

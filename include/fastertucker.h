@@ -54,6 +54,7 @@ typedef enum {
 /* ft_desc.flags */
 #define FT_KEEP_HOST 1 /* keep the host copy of the plan after upload (ft_plan_host_csr) */
 #define FT_WITH_PERM 2 /* keep element permutations on the device (ft_forward, ft_grad with upstream) */
+#define FT_NO_FIBER_SHARE 4 /* compute g for every element instead of once per fiber (Section 3.2); same results */
 
 /* Shape of the problem and of the plan. */
 typedef struct {
@@ -63,7 +64,7 @@ typedef struct {
   int32_t R;                    /* core rank */
   int64_t nnz;                  /* |Omega|, 0..2^32-1 */
   int32_t chunk;                /* rows with more elements are split into chunks of this many (0: 512) */
-  int32_t fanin;                /* chunk maps folded per combine step (0: 64) */
+  int32_t fanin;                /* chunk maps folded per combine step (0: 64; at most 64 for J <= 16, 16 above) */
   int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM */
 } ft_desc;
 
@@ -101,6 +102,8 @@ typedef struct {
   int64_t chunks;        /* chunks of heavy rows, first chunks included */
   int64_t segments;      /* pieces of rows used by the core, loss and gradient passes */
   int32_t combine_levels;
+  int32_t fiber_shared;  /* 1 if the factor pass shares g per fiber in this mode */
+  int64_t fibers;        /* mode-m fibers: distinct (i_n, n != m) */
 } ft_mode_info;
 
 typedef struct ft_plan ft_plan;
@@ -233,7 +236,8 @@ typedef enum {
   FT_K_SEGSUM = 4,         /* core and gradient segment sums */
   FT_K_REDUCE = 5,         /* partial-sum reduction and B step */
   FT_K_LOSS = 6,           /* loss and forward gather */
-  FT_K_COUNT = 7
+  FT_K_FIBER_G = 7,        /* shared g per fiber */
+  FT_K_COUNT = 8
 } ft_kernel_id;
 ft_status ft_profile_enable(ft_plan* plan, int32_t enable);
 ft_status ft_profile_read(ft_plan* plan, double* ms, int64_t* launches);

@@ -10,6 +10,7 @@ MAX_ORDER = 10
 
 FT_KEEP_HOST = 1
 FT_WITH_PERM = 2
+FT_NO_FIBER_SHARE = 4
 
 STATUS = {
     0: "FT_OK",
@@ -88,10 +89,12 @@ class FtModeInfo(ctypes.Structure):
         ("chunks", ctypes.c_int64),
         ("segments", ctypes.c_int64),
         ("combine_levels", ctypes.c_int32),
+        ("fiber_shared", ctypes.c_int32),
+        ("fibers", ctypes.c_int64),
     ]
 
 
-KERNELS = ["factor_compose", "factor_apply", "combine", "refresh", "segsum", "reduce", "loss"]
+KERNELS = ["factor_compose", "factor_apply", "combine", "refresh", "segsum", "reduce", "loss", "fiber_g"]
 
 
 class FtError(RuntimeError):

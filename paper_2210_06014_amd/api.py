@@ -29,7 +29,8 @@ class Plan:
 
     coords: int32 [order][nnz] (host), vals: float32 [nnz] (host)."""
 
-    def __init__(self, dims, J, R, coords, vals, chunk=0, fanin=0, keep_host=False, with_perm=False, upload=True):
+    def __init__(self, dims, J, R, coords, vals, chunk=0, fanin=0, keep_host=False, with_perm=False, upload=True,
+                 fiber_share=True):
         lib = load()
         coords = np.ascontiguousarray(coords, dtype=np.int32)
         vals = np.ascontiguousarray(vals, dtype=np.float32)
@@ -46,7 +47,8 @@ class Plan:
         d.nnz = int(coords.shape[1])
         d.chunk = int(chunk)
         d.fanin = int(fanin)
-        d.flags = (_lib.FT_KEEP_HOST if keep_host else 0) | (_lib.FT_WITH_PERM if with_perm else 0)
+        d.flags = ((_lib.FT_KEEP_HOST if keep_host else 0) | (_lib.FT_WITH_PERM if with_perm else 0)
+                   | (0 if fiber_share else _lib.FT_NO_FIBER_SHARE))
         self.dims = [int(x) for x in dims]
         self.order = order
         self.J = Js[0]

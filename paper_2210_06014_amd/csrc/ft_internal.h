@@ -56,6 +56,8 @@ struct ModeHost {
   std::vector<std::vector<CItem>> levels;
   std::vector<Seg> segs;
   std::vector<int64_t> seg_ptr;   // I+1: segments of row i are seg_ptr[i]..seg_ptr[i+1]-1
+  std::vector<int32_t> fid;       // nnz: fiber of the element at each CSR position
+  std::vector<int32_t> fib_idx;   // (N-1) x fibers: fixed indices of each fiber (modes m+1, ..., m-1)
 };
 
 struct ModeDev {
@@ -68,6 +70,8 @@ struct ModeDev {
   CItem* levels = nullptr;  // all levels back to back
   Seg* segs = nullptr;
   int64_t* seg_ptr = nullptr;
+  int32_t* fid = nullptr;
+  int32_t* fib_idx = nullptr;
 };
 
 struct ModeMeta {
@@ -80,6 +84,8 @@ struct ModeMeta {
   std::vector<int64_t> level_len;
   int64_t n_level_out0 = 0;        // outputs of level 0 (ping-pong buffer size)
   int64_t n_segs = 0;
+  int64_t n_fibers = 0;
+  bool use_fiber = false;
   ft_mode_info info{};
 };
 
@@ -102,13 +108,14 @@ struct ft_plan {
   bool uploaded = false;
   // scratch shared by all modes (sized for the largest)
   float* maps = nullptr;       // map slots (level ping-pong region 0 and 1)
-  int64_t* map_cnt = nullptr;
+  double* map_scale = nullptr; // rho^(elements) of each map
   int64_t maps_region1 = 0;    // slot offset of region 1
   float* hvec = nullptr;       // heavy rows' head vectors
   float* partials = nullptr;   // per-workgroup partial sums (core/grad)
   double* dpartials = nullptr; // per-workgroup FP64 partial sums (loss)
   float* tseg = nullptr;       // per-segment row sums (gradient)
   float* gbuf = nullptr;       // J x R gradient buffer
+  float* gfib = nullptr;       // fibers x J: the shared g of each fiber (factor pass)
   size_t device_bytes = 0;
   // kernel timing (ft_profile_enable); launches on a const plan append to it
   mutable bool prof_on = false;
@@ -154,4 +161,5 @@ hipError_t launch_forward(const ft_plan* P, const ft_params* p, float* out, hipS
 hipError_t launch_grad(const ft_plan* P, const ft_params* p, const float* upstream, float* const* gA,
                        float* const* gB, hipStream_t s);
 bool supported(int N, int J, int R);
+int max_fanin(int J);  // largest combine fan-in the kernels hold in LDS
 }  // namespace ft

@@ -10,7 +10,9 @@
 //  * C refresh: v_mfma_f32_16x16x4_f32 tiles of 16 rows.
 // No floating-point atomics: every reduction runs in a fixed order.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
+#include <unordered_map>
 
 #include "ft_internal.h"
 
@@ -272,18 +274,17 @@ __device__ __forceinline__ void shared_g(const float (&Bw)[J >= 16 ? J / 16 : 1]
   }
 }
 
+// The shared intermediate of Section 3.2: g_f = B(m) w_f once per mode-m
+// fiber f (w_f = prod_{n != m} C(n)[i_n, :] is the same for every element of
+// the fiber).  Same lane layout and operation order as the per-element path,
+// so the factor pass gives the same bits either way.  16 fibers per group.
 template <int N, int J, int R, class T>
-__global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ items, int64_t n_items,
-                                                      const int32_t* __restrict__ idx, int64_t nnz,
-                                                      const float* __restrict__ val, CPtrs<N, T> cp,
-                                                      const T* __restrict__ Bm, float* __restrict__ Am,
-                                                      float* __restrict__ hvec, float lr, float c1) {
+__global__ __launch_bounds__(256) void k_fiber_g(const int32_t* __restrict__ fib_idx, int64_t nfib, CPtrs<N, T> cp,
+                                                 const T* __restrict__ Bm, float* __restrict__ gfib) {
   constexpr int E = J >= 16 ? J / 16 : 1;
   constexpr int RE = R >= 16 ? R / 16 : 1;
   const int l = threadIdx.x & 15;
-  const int64_t gid = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
-  FItem it{0, 0, 0, 0, 0};
-  if (gid < n_items) it = items[gid];
+  const int64_t f0 = ((int64_t)blockIdx.x * 16 + (threadIdx.x >> 4)) * 16;
   float Bw[E][R];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -291,6 +292,52 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
 #pragma unroll
     for (int r = 0; r < R; ++r) Bw[e][r] = j < J ? to_f(Bm[j * R + r]) : 0.f;
   }
+  const int len = (int)max<int64_t>(0, min<int64_t>(16, nfib - f0));
+  const int64_t f = min(f0 + l, nfib - 1);
+  int ixb[N - 1];
+#pragma unroll
+  for (int k = 0; k < N - 1; ++k) ixb[k] = len > 0 ? fib_idx[(int64_t)k * nfib + f] * (int)(R * sizeof(T)) : 0;
+  float w[16][RE];
+  gather_w<N, R, T>(cp, ixb, l, 0, len, w);
+  static_for<0, 16>([&](auto S) {
+    constexpr int s = decltype(S)::value;
+    float g[E];
+    shared_g<J, R>(Bw, w[s], g);
+    if (s < len) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int j = l + 16 * e;
+        if (j < J) gfib[(f0 + s) * J + j] = g[e];
+      }
+    }
+  });
+}
+
+template <int N, int J, int R, class T, bool FIB>
+__global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ items, int64_t n_items,
+                                                      const int32_t* __restrict__ idx, int64_t nnz,
+                                                      const float* __restrict__ val, CPtrs<N, T> cp,
+                                                      const T* __restrict__ Bm, float* __restrict__ Am,
+                                                      float* __restrict__ hvec, float lr, float c1,
+                                                      const int32_t* __restrict__ fid, const float* __restrict__ gfib) {
+  constexpr int E = J >= 16 ? J / 16 : 1;
+  constexpr int RE = R >= 16 ? R / 16 : 1;
+  const int l = threadIdx.x & 15;
+  float Bw[E][R];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = l + 16 * e;
+#pragma unroll
+    for (int r = 0; r < R; ++r) Bw[e][r] = (!FIB && j < J) ? to_f(Bm[j * R + r]) : 0.f;
+  }
+  // Persistent groups: the four groups of a wavefront take four consecutive
+  // items (similar lengths, the lists are sorted) and then stride by the grid,
+  // so B(m) is loaded once per group.  The trip count is wave-uniform.
+  const int64_t G = (int64_t)gridDim.x * 16;
+  for (int64_t base = (int64_t)blockIdx.x * 16 + ((threadIdx.x >> 6) << 2); base < n_items; base += G) {
+  const int64_t gid = base + ((threadIdx.x >> 4) & 3);
+  FItem it{0, 0, 0, 0, 0};
+  if (gid < n_items) it = items[gid];
   // The row is carried in FP64 registers and rounded to FP32 once when
   // stored: the decay step lr*lam*a is about a hundred ulps of a, nearly the
   // same every step, so FP32 rounding of the running state would accumulate
@@ -308,17 +355,37 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
     // past the end: clamp to the item's last element (valid address); those
     // steps are neutralised below (w = 0, no decay)
     const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
-    int ix[N - 1];
-#pragma unroll
-    for (int k = 0; k < N - 1; ++k)
-      ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (int)(R * sizeof(T)) : 0;
     const float xv = it.len > 0 ? val[p] : 0.f;
-    float w[16][RE];
-    gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
+    // phase 1: w of the 16 elements (or, with fibers, their precomputed g)
+    float w[16][FIB ? E : RE];
+    if constexpr (FIB) {
+      const int fv = it.len > 0 ? fid[p] : 0;
+      static_for<0, 16>([&](auto S) {
+        constexpr int s = decltype(S)::value;
+        const int64_t fb = (int64_t)bcast16i<s>(fv) * J;
+        const bool sv = (t0 + s) < it.len;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int j = l + 16 * e;
+          w[s][e] = (sv && j < J) ? gfib[fb + j] : 0.f;
+        }
+      });
+    } else {
+      int ix[N - 1];
+#pragma unroll
+      for (int k = 0; k < N - 1; ++k)
+        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (int)(R * sizeof(T)) : 0;
+      gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
+    }
     static_for<0, 16>([&](auto S) {
       constexpr int s = decltype(S)::value;
       float g[E];
-      shared_g<J, R>(Bw, w[s], g);
+      if constexpr (FIB) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) g[e] = w[s][e];
+      } else {
+        shared_g<J, R>(Bw, w[s], g);
+      }
       float pr = 0.f;
 #pragma unroll
       for (int e = 0; e < E; ++e) pr = fmaf((float)a[e], g[e], pr);
@@ -345,6 +412,7 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
       }
     }
   }
+  }
 }
 
 // Chunk maps.  With rho = 1 - lr lam and gp = lr / rho, one step is
@@ -353,26 +421,33 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
 //     Nm <- Nm - gp g (g + Nm^T g)^T     (Nm = prod (I - gp g g^T) - I)
 //     v  <- v + (-lr lam) v + lr (x - v.g) g
 // (v is the state reached from a = 0).  Lane j keeps column j of Nm.
-template <int N, int J, int R, class T>
+template <int N, int J, int R, class T, bool FIB>
 __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict__ items, int64_t n_items,
                                                         const int32_t* __restrict__ idx, int64_t nnz,
                                                         const float* __restrict__ val, CPtrs<N, T> cp,
                                                         const T* __restrict__ Bm, float* __restrict__ maps,
-                                                        int64_t* __restrict__ map_cnt, float lr, float c1, float gp) {
+                                                        double* __restrict__ map_scale, float lr, float c1, float gp,
+                                                        double rho, const int32_t* __restrict__ fid,
+                                                        const float* __restrict__ gfib) {
   constexpr int E = J >= 16 ? J / 16 : 1;
   constexpr int RE = R >= 16 ? R / 16 : 1;
   constexpr int MS = J * J + J;
   const int l = threadIdx.x & 15;
-  const int64_t gid = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
-  FItem it{0, 0, 0, 0, 0};
-  if (gid < n_items) it = items[gid];
   float Bw[E][R];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int j = l + 16 * e;
 #pragma unroll
-    for (int r = 0; r < R; ++r) Bw[e][r] = j < J ? to_f(Bm[j * R + r]) : 0.f;
+    for (int r = 0; r < R; ++r) Bw[e][r] = (!FIB && j < J) ? to_f(Bm[j * R + r]) : 0.f;
   }
+  // Persistent groups: the four groups of a wavefront take four consecutive
+  // items (similar lengths, the lists are sorted) and then stride by the grid,
+  // so B(m) is loaded once per group.  The trip count is wave-uniform.
+  const int64_t G = (int64_t)gridDim.x * 16;
+  for (int64_t base = (int64_t)blockIdx.x * 16 + ((threadIdx.x >> 6) << 2); base < n_items; base += G) {
+  const int64_t gid = base + ((threadIdx.x >> 4) & 3);
+  FItem it{0, 0, 0, 0, 0};
+  if (gid < n_items) it = items[gid];
   float Nc[E][J];
   float v[E];
 #pragma unroll
@@ -388,17 +463,37 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
     // past the end: clamp to the item's last element (valid address); those
     // steps are neutralised below (w = 0, no decay)
     const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
-    int ix[N - 1];
-#pragma unroll
-    for (int k = 0; k < N - 1; ++k)
-      ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (int)(R * sizeof(T)) : 0;
     const float xv = it.len > 0 ? val[p] : 0.f;
-    float w[16][RE];
-    gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
+    // phase 1: w of the 16 elements (or, with fibers, their precomputed g)
+    float w[16][FIB ? E : RE];
+    if constexpr (FIB) {
+      const int fv = it.len > 0 ? fid[p] : 0;
+      static_for<0, 16>([&](auto S) {
+        constexpr int s = decltype(S)::value;
+        const int64_t fb = (int64_t)bcast16i<s>(fv) * J;
+        const bool sv = (t0 + s) < it.len;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int j = l + 16 * e;
+          w[s][e] = (sv && j < J) ? gfib[fb + j] : 0.f;
+        }
+      });
+    } else {
+      int ix[N - 1];
+#pragma unroll
+      for (int k = 0; k < N - 1; ++k)
+        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (int)(R * sizeof(T)) : 0;
+      gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
+    }
     static_for<0, 16>([&](auto S) {
       constexpr int s = decltype(S)::value;
       float g[E];
-      shared_g<J, R>(Bw, w[s], g);
+      if constexpr (FIB) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) g[e] = w[s][e];
+      } else {
+        shared_g<J, R>(Bw, w[s], g);
+      }
       constexpr int JK = J >= 16 ? 16 : J;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -435,86 +530,105 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
         dst[J * J + j] = v[e];
       }
     }
-    if (l == 0) map_cnt[it.slot] = it.len;
+    if (l == 0) map_scale[it.slot] = pow(rho, (double)it.len);
+  }
   }
 }
 
-// Fold `count` consecutive maps (earliest first) into one:
+// Fold `count` consecutive maps (earliest first) into one, as a binary tree in
+// LDS (fixed bracketing: pairs (0,1), (2,3), ... then (0,2), ... so that a
+// later map is always applied after an earlier one):
 //   (s2, N2, v2) o (s1, N1, v1) = (s1 s2, N1 + N2 + N2 N1, s2 (v1 + N2 v1) + v2),
-// where s = rho^count.  The last fold of a row applies the map to the row's
-// head vector (the state after its first chunk) and writes A(m).
+// with s = rho^length kept in FP64.  The last fold of a row applies the map to
+// the row's head vector (the state after its first chunk) and writes A(m).
+template <int J>
+constexpr int combine_fanin() {
+  return J <= 16 ? 64 : 16;  // maps held in LDS by one workgroup
+}
+
 template <int J>
 __global__ __launch_bounds__(256) void k_combine(const CItem* __restrict__ items, float* __restrict__ maps,
-                                                 int64_t* __restrict__ map_cnt, const float* __restrict__ hvec,
-                                                 float* __restrict__ Am, double rho) {
+                                                 double* __restrict__ map_scale, const float* __restrict__ hvec,
+                                                 float* __restrict__ Am) {
   constexpr int MS = J * J + J;
-  constexpr int PER = (J * J + 255) / 256;
-  __shared__ float accN[J * J], accV[J], curN[J * J], curV[J];
+  constexpr int F = combine_fanin<J>();
+  constexpr int RMAX = (F / 2 * J * J + 255) / 256;  // matrix entries per thread at the widest level
+  constexpr int VMAX = (F / 2 * J + 255) / 256;      // vector entries per thread at the widest level
+  __shared__ float buf[F * MS];
+  __shared__ double sc[F];
   const CItem it = items[blockIdx.x];
   const int t = threadIdx.x;
-  const float* src0 = maps + it.in_off * MS;
-  for (int k = t; k < MS; k += 256) {
-    const float x = src0[k];
-    if (k < J * J)
-      accN[k] = x;
-    else
-      accV[k - J * J] = x;
+  const int count = it.count;
+  {
+    const float* src = maps + it.in_off * MS;
+    for (int k = t; k < count * MS; k += 256) buf[k] = src[k];
+    if (t < count) sc[t] = map_scale[it.in_off + t];
   }
-  int64_t cnt = map_cnt[it.in_off];
   __syncthreads();
-  for (int c = 1; c < it.count; ++c) {
-    const int64_t slot = it.in_off + c;
-    const float* src = maps + slot * MS;
-    for (int k = t; k < MS; k += 256) {
-      const float x = src[k];
-      if (k < J * J)
-        curN[k] = x;
-      else
-        curV[k - J * J] = x;
-    }
-    const int64_t ck = map_cnt[slot];
-    __syncthreads();
-    float nn[PER];
+  for (int stride = 1; stride < count; stride *= 2) {
+    const int pairs = (count - stride + 2 * stride - 1) / (2 * stride);  // a = 2 k stride, b = a + stride < count
+    float res[RMAX];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
+    for (int u = 0; u < RMAX; ++u) {
       const int e = t + 256 * u;
-      if (e < J * J) {
-        const int i = e % J, j = e / J;
-        float s = 0.f;
+      if (e < pairs * J * J) {
+        const int pr = e / (J * J), ij = e % (J * J);
+        const int i = ij % J, j = ij / J;
+        const float* Na = buf + (2 * pr * stride) * MS;
+        const float* Nb = Na + stride * MS;
+        float acc = 0.f;
 #pragma unroll
-        for (int q = 0; q < J; ++q) s = fmaf(curN[q * J + i], accN[j * J + q], s);
-        nn[u] = (accN[e] + curN[e]) + s;
+        for (int q = 0; q < J; ++q) acc = fmaf(Nb[q * J + i], Na[j * J + q], acc);
+        res[u] = (Na[ij] + Nb[ij]) + acc;
       }
     }
-    float vv = 0.f;
-    if (t < J) {
-      float s = 0.f;
+    float vres[VMAX];
+    double sres[VMAX];
 #pragma unroll
-      for (int q = 0; q < J; ++q) s = fmaf(curN[q * J + t], accV[q], s);
-      const double sk = pow(rho, (double)ck);
-      vv = (float)(sk * ((double)accV[t] + (double)s)) + curV[t];
+    for (int u = 0; u < VMAX; ++u) {
+      const int e = t + 256 * u;
+      if (e < pairs * J) {
+        const int pr = e / J, i = e % J;
+        const float* Na = buf + (2 * pr * stride) * MS;
+        const float* Nb = Na + stride * MS;
+        float acc = 0.f;
+#pragma unroll
+        for (int q = 0; q < J; ++q) acc = fmaf(Nb[q * J + i], Na[J * J + q], acc);
+        const double sb = sc[2 * pr * stride + stride];
+        vres[u] = (float)(sb * ((double)Na[J * J + i] + (double)acc)) + Nb[J * J + i];
+        sres[u] = sc[2 * pr * stride] * sb;
+      }
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
+    for (int u = 0; u < RMAX; ++u) {
       const int e = t + 256 * u;
-      if (e < J * J) accN[e] = nn[u];
+      if (e < pairs * J * J) {
+        const int pr = e / (J * J), ij = e % (J * J);
+        buf[(2 * pr * stride) * MS + ij] = res[u];
+      }
     }
-    if (t < J) accV[t] = vv;
-    cnt += ck;
+#pragma unroll
+    for (int u = 0; u < VMAX; ++u) {
+      const int e = t + 256 * u;
+      if (e < pairs * J) {
+        const int pr = e / J, i = e % J;
+        buf[(2 * pr * stride) * MS + J * J + i] = vres[u];
+        if (i == 0) sc[2 * pr * stride] = sres[u];
+      }
+    }
     __syncthreads();
   }
   if (it.out_off >= 0) {
     float* dst = maps + it.out_off * MS;
-    for (int k = t; k < MS; k += 256) dst[k] = k < J * J ? accN[k] : accV[k - J * J];
-    if (t == 0) map_cnt[it.out_off] = cnt;
+    for (int k = t; k < MS; k += 256) dst[k] = buf[k];
+    if (t == 0) map_scale[it.out_off] = sc[0];
   } else if (t < J) {
     const float* a0 = hvec + (int64_t)it.heavy * J;
-    float s = 0.f;
+    float acc = 0.f;
 #pragma unroll
-    for (int q = 0; q < J; ++q) s = fmaf(accN[q * J + t], a0[q], s);
-    const double sc = pow(rho, (double)cnt);
-    Am[(int64_t)it.row * J + t] = (float)(sc * ((double)a0[t] + (double)s)) + accV[t];
+    for (int q = 0; q < J; ++q) acc = fmaf(buf[q * J + t], a0[q], acc);
+    Am[(int64_t)it.row * J + t] = (float)(sc[0] * ((double)a0[t] + (double)acc)) + buf[J * J + t];
   }
 }
 
@@ -844,30 +958,73 @@ CPtrs<N, T> others(const ft_params* p, int m) {
   return c;
 }
 
-template <int N, int J, int R, class T>
-hipError_t factor_impl(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
+// Workgroups that fit on the device at once for a 256-thread kernel (from the
+// occupancy query, cached per kernel).  Persistent grids use at most this
+// many, so that no workgroup starts after the others have finished.
+int resident_blocks(const void* kernel) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto f = cache.find(kernel);
+  if (f != cache.end()) return f->second;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || cus <= 0 || per_cu <= 0) {
+    cus = 256;
+    per_cu = 2;
+  }
+  const int r = cus * per_cu;
+  cache.emplace(kernel, r);
+  return r;
+}
+
+// One item per 16-lane group: the hardware dispatcher balances the items
+// (measured faster than a resident persistent grid for these kernels).
+unsigned factor_blocks(const void* kernel, int64_t n_items) {
+  (void)kernel;
+  return (unsigned)std::max<int64_t>(1, (n_items + 15) / 16);
+}
+
+template <int N, int J, int R, class T, bool FIB>
+hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
   const ModeMeta& M = P->meta[m];
   const ModeDev& D = P->dev[m];
   const CPtrs<N, T> cp = others<N, T>(p, m);
   const T* Bm = Store<T>::B(p, m);
   const double rho = 1.0 - lr * lam;
   const float flr = (float)lr, c1 = (float)(-lr * lam), gp = (float)(lr / rho);
+  if (FIB) {
+    KTimer tm(P, FT_K_FIBER_G, s);
+    const int64_t groups = (M.n_fibers + 15) / 16;
+    hipLaunchKernelGGL((k_fiber_g<N, J, R, T>), dim3((unsigned)((groups + 15) / 16)), dim3(256), 0, s, D.fib_idx,
+                       M.n_fibers, cp, Bm, P->gfib);
+  }
   if (M.n_compose > 0) {
     KTimer tm(P, FT_K_FACTOR_COMPOSE, s);
-    hipLaunchKernelGGL((k_factor_compose<N, J, R, T>), dim3((unsigned)((M.n_compose + 15) / 16)), dim3(256), 0, s,
-                       D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm, P->maps, P->map_cnt, flr, c1, gp);
+    hipLaunchKernelGGL((k_factor_compose<N, J, R, T, FIB>),
+                       dim3(factor_blocks((const void*)k_factor_compose<N, J, R, T, FIB>, M.n_compose)), dim3(256), 0,
+                       s, D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm, P->maps, P->map_scale, flr, c1, gp,
+                       rho, D.fid, P->gfib);
   }
   if (M.n_apply > 0) {
     KTimer tm(P, FT_K_FACTOR_APPLY, s);
-    hipLaunchKernelGGL((k_factor_apply<N, J, R, T>), dim3((unsigned)((M.n_apply + 15) / 16)), dim3(256), 0, s,
-                       D.apply, M.n_apply, D.idx, P->nnz, D.val, cp, Bm, p->A[m], P->hvec, flr, c1);
+    hipLaunchKernelGGL((k_factor_apply<N, J, R, T, FIB>),
+                       dim3(factor_blocks((const void*)k_factor_apply<N, J, R, T, FIB>, M.n_apply)), dim3(256), 0, s,
+                       D.apply, M.n_apply, D.idx, P->nnz, D.val, cp, Bm, p->A[m], P->hvec, flr, c1, D.fid, P->gfib);
   }
   for (size_t L = 0; L < M.level_len.size(); ++L) {
     KTimer tm(P, FT_K_COMBINE, s);
     hipLaunchKernelGGL((k_combine<J>), dim3((unsigned)M.level_len[L]), dim3(256), 0, s, D.levels + M.level_off[L],
-                       P->maps, P->map_cnt, P->hvec, p->A[m], rho);
+                       P->maps, P->map_scale, P->hvec, p->A[m]);
   }
   return hipGetLastError();
+}
+
+template <int N, int J, int R, class T>
+hipError_t factor_impl(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
+  return P->meta[m].use_fiber ? factor_launch<N, J, R, T, true>(P, m, p, lr, lam, s)
+                              : factor_launch<N, J, R, T, false>(P, m, p, lr, lam, s);
 }
 
 hipError_t reduce_partials(const ft_plan* P, int nparts, float* Bm, float* Gout, float lr, float lam, float inv,
@@ -882,9 +1039,9 @@ hipError_t reduce_partials(const ft_plan* P, int nparts, float* Bm, float* Gout,
   return hipGetLastError();
 }
 
-int seg_blocks(int64_t nseg) {
+int seg_blocks(const void* kernel, int64_t nseg) {
   int64_t b = (nseg + 3) / 4;
-  if (b > kPartials) b = kPartials;
+  b = std::min<int64_t>(b, std::min(kPartials, resident_blocks(kernel)));
   if (b < 1) b = 1;
   return (int)b;
 }
@@ -897,7 +1054,9 @@ hipError_t segsum_impl(const ft_plan* P, int m, const ft_params* p, int mode, co
   const CPtrs<N, T> cp = others<N, T>(p, m);
   const T* Cm = Store<T>::C(p, m);
   const T* Am = Store<T>::A(p, m);
-  const int nb = seg_blocks(M.n_segs);
+  const void* kern = mode == 0 ? (const void*)k_segsum<N, J, R, 0, T>
+                     : mode == 1 ? (const void*)k_segsum<N, J, R, 1, T> : (const void*)k_segsum<N, J, R, 2, T>;
+  const int nb = seg_blocks(kern, M.n_segs);
   *nblocks = nb;
   KTimer tm(P, FT_K_SEGSUM, s);
   if (mode == 0)
@@ -918,7 +1077,7 @@ hipError_t loss_impl(const ft_plan* P, const ft_params* p, double lam_a, double 
   const ModeMeta& M = P->meta[0];
   const ModeDev& D = P->dev[0];
   const CPtrs<N, T> cp = others<N, T>(p, 0);
-  const int nb = seg_blocks(M.n_segs);
+  const int nb = seg_blocks((const void*)k_loss<N, R, T>, M.n_segs);
   {
     KTimer tm(P, FT_K_LOSS, s);
     hipLaunchKernelGGL((k_loss<N, R, T>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp,
@@ -962,6 +1121,8 @@ hipError_t grad_rows_impl(const ft_plan* P, int m, const ft_params* p, float* gA
 bool bf16(const ft_params* p) { return p->storage == FT_STORE_BF16; }
 
 }  // namespace
+
+int max_fanin(int J) { return J <= 8 ? combine_fanin<8>() : J <= 16 ? combine_fanin<16>() : combine_fanin<32>(); }
 
 bool supported(int N, int J, int R) {
   switch (key(N, J, R)) {

@@ -99,11 +99,48 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   try {
     std::vector<uint32_t> order((size_t)nnz), tmp((size_t)nnz);
     for (int64_t j = 0; j < nnz; ++j) order[j] = (uint32_t)j;
-    // least significant first: i_{m-1}, ..., i_{m+1}, then i_m
-    for (int k = N - 1; k >= 0; --k) {
+    // least significant first: i_{m-1}, ..., i_{m+1} (this is the order of the
+    // mode-m fibers), then i_m
+    for (int k = N - 1; k >= 1; --k) {
       int n = (m + k) % N;
       radix_by_column(coords + (int64_t)n * nnz, P->desc.dims[n], order, tmp, T);
     }
+    // fibers: runs of equal (i_{m+1}, ..., i_{m-1}) in the current order
+    std::vector<uint32_t> fid_of((size_t)nnz);
+    {
+      const int64_t per = (nnz + T - 1) / T;
+      std::vector<int64_t> starts((size_t)T + 1, 0);
+      auto is_start = [&](int64_t j) {
+        if (j == 0) return true;
+        const uint32_t x = order[j], y = order[j - 1];
+        for (int k = 1; k < N; ++k) {
+          const int64_t base = (int64_t)((m + k) % N) * nnz;
+          if (coords[base + x] != coords[base + y]) return true;
+        }
+        return false;
+      };
+      parallel_for(T, [&](int t) {
+        int64_t lo = t * per, hi = std::min(nnz, lo + per), c = 0;
+        for (int64_t j = lo; j < hi; ++j) c += is_start(j);
+        starts[t + 1] = c;
+      });
+      for (int t = 0; t < T; ++t) starts[t + 1] += starts[t];
+      const int64_t nfib = starts[T];
+      H.fib_idx.assign((size_t)(N - 1) * nfib, 0);
+      parallel_for(T, [&](int t) {
+        int64_t lo = t * per, hi = std::min(nnz, lo + per), f = starts[t] - 1;
+        for (int64_t j = lo; j < hi; ++j) {
+          if (is_start(j)) {
+            ++f;
+            for (int k = 1; k < N; ++k)
+              H.fib_idx[(size_t)(k - 1) * nfib + f] = coords[(int64_t)((m + k) % N) * nnz + order[j]];
+          }
+          fid_of[order[j]] = (uint32_t)f;
+        }
+      });
+      P->meta[m].n_fibers = nfib;
+    }
+    radix_by_column(coords + (int64_t)m * nnz, P->desc.dims[m], order, tmp, T);
     tmp.clear();
     tmp.shrink_to_fit();
     H.row_ptr.assign((size_t)I + 1, 0);
@@ -113,6 +150,7 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
     H.idx.resize((size_t)(N - 1) * nnz);
     H.val.resize((size_t)nnz);
     H.perm.resize((size_t)nnz);
+    H.fid.resize((size_t)nnz);
     const int64_t per = (nnz + T - 1) / T;
     parallel_for(T, [&](int t) {
       int64_t lo = t * per, hi = std::min(nnz, lo + per);
@@ -121,6 +159,7 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
         for (int k = 1; k < N; ++k) H.idx[(size_t)(k - 1) * nnz + p] = coords[(int64_t)((m + k) % N) * nnz + x];
         H.val[p] = vals[x];
         H.perm[p] = x;
+        H.fid[p] = (int32_t)fid_of[x];
       }
     });
   } catch (const std::bad_alloc&) {
@@ -208,6 +247,15 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
     H.seg_ptr[i + 1] = (int64_t)H.segs.size();
   }
 
+  // share g per fiber when fibers hold 4/3 elements or more on average
+  M.use_fiber = !(P->desc.flags & FT_NO_FIBER_SHARE) && M.n_fibers > 0 && M.n_fibers * 4 <= nnz * 3 &&
+                M.n_fibers <= 0x7FFFFFFF;
+  if (!M.use_fiber) {
+    H.fid.clear();
+    H.fid.shrink_to_fit();
+    H.fib_idx.clear();
+    H.fib_idx.shrink_to_fit();
+  }
   M.n_compose = (int64_t)H.compose.size();
   M.n_apply = (int64_t)H.apply.size();
   M.n_heavy = n_heavy;
@@ -229,6 +277,8 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   inf.chunks = (int64_t)head.size() + n_maps;
   inf.segments = M.n_segs;
   inf.combine_levels = (int32_t)H.levels.size();
+  inf.fibers = M.n_fibers;
+  inf.fiber_shared = M.use_fiber ? 1 : 0;
   return FT_OK;
 }
 
@@ -284,7 +334,7 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
   P->R = d->R;
   P->nnz = nnz;
   P->chunk = d->chunk ? d->chunk : 512;
-  P->fanin = d->fanin ? d->fanin : 64;
+  P->fanin = std::min(d->fanin ? d->fanin : 64, max_fanin(d->J[0]));
   try {
     P->meta.resize(N);
     P->host.resize(N);
@@ -326,15 +376,15 @@ hipError_t alloc(T** dst, size_t count, size_t& bytes) {
 void free_dev(ft_plan* P) {
   for (auto& D : P->dev) {
     (void)hipFree(D.row_ptr); (void)hipFree(D.idx); (void)hipFree(D.val); (void)hipFree(D.perm);
-    (void)hipFree(D.compose);
+    (void)hipFree(D.compose); (void)hipFree(D.fid); (void)hipFree(D.fib_idx);
     (void)hipFree(D.apply); (void)hipFree(D.levels); (void)hipFree(D.segs); (void)hipFree(D.seg_ptr);
     D = ModeDev{};
   }
-  (void)hipFree(P->maps); (void)hipFree(P->map_cnt); (void)hipFree(P->hvec); (void)hipFree(P->partials);
+  (void)hipFree(P->maps); (void)hipFree(P->map_scale); (void)hipFree(P->hvec); (void)hipFree(P->partials);
   (void)hipFree(P->dpartials);
-  (void)hipFree(P->tseg); (void)hipFree(P->gbuf);
-  P->maps = nullptr; P->map_cnt = nullptr; P->hvec = nullptr; P->partials = nullptr; P->dpartials = nullptr;
-  P->tseg = nullptr; P->gbuf = nullptr;
+  (void)hipFree(P->tseg); (void)hipFree(P->gbuf); (void)hipFree(P->gfib);
+  P->maps = nullptr; P->map_scale = nullptr; P->hvec = nullptr; P->partials = nullptr; P->dpartials = nullptr;
+  P->tseg = nullptr; P->gbuf = nullptr; P->gfib = nullptr;
   P->device_bytes = 0;
   P->uploaded = false;
 }
@@ -347,7 +397,7 @@ extern "C" ft_status ft_plan_upload(ft_plan* P, void* stream) {
   (void)stream;
   size_t bytes = 0;
   hipError_t e = hipSuccess;
-  int64_t max_slots = 1, max_heavy = 1, max_segs = 1;
+  int64_t max_slots = 1, max_heavy = 1, max_segs = 1, max_fib = 0;
   for (int m = 0; m < P->N && e == hipSuccess; ++m) {
     ModeHost& H = P->host[m];
     ModeDev& D = P->dev[m];
@@ -368,18 +418,22 @@ extern "C" ft_status ft_plan_upload(ft_plan* P, void* stream) {
     }
     if (e == hipSuccess) e = upload(&D.segs, H.segs, bytes);
     if (e == hipSuccess) e = upload(&D.seg_ptr, H.seg_ptr, bytes);
+    if (e == hipSuccess && M.use_fiber) e = upload(&D.fid, H.fid, bytes);
+    if (e == hipSuccess && M.use_fiber) e = upload(&D.fib_idx, H.fib_idx, bytes);
+    if (M.use_fiber) max_fib = std::max(max_fib, M.n_fibers);
     max_slots = std::max(max_slots, M.n_maps + M.n_level_out0);
     max_heavy = std::max(max_heavy, M.n_heavy);
     max_segs = std::max(max_segs, M.n_segs);
   }
   const int J = P->J, R = P->R;
   if (e == hipSuccess) e = alloc(&P->maps, (size_t)max_slots * (J * J + J), bytes);
-  if (e == hipSuccess) e = alloc(&P->map_cnt, (size_t)max_slots, bytes);
+  if (e == hipSuccess) e = alloc(&P->map_scale, (size_t)max_slots, bytes);
   if (e == hipSuccess) e = alloc(&P->hvec, (size_t)max_heavy * J, bytes);
   if (e == hipSuccess) e = alloc(&P->partials, (size_t)(kPartials + kPartials / 32 + 1) * J * R, bytes);
   if (e == hipSuccess) e = alloc(&P->dpartials, (size_t)kPartials + 2 * FT_MAX_ORDER * 256, bytes);
   if (e == hipSuccess) e = alloc(&P->tseg, (size_t)max_segs * R, bytes);
   if (e == hipSuccess) e = alloc(&P->gbuf, (size_t)J * R, bytes);
+  if (e == hipSuccess && max_fib > 0) e = alloc(&P->gfib, (size_t)max_fib * J, bytes);
   if (e != hipSuccess) {
     free_dev(P);
     return fail(FT_ERR_HIP, std::string("device allocation or copy failed: ") + hipGetErrorString(e));

@@ -209,3 +209,28 @@ def test_empty_and_tiny():
     for n in range(3):
         np.testing.assert_allclose(to_np(prm.A[n]), orc.A[n], rtol=1e-5, atol=1e-7)
         np.testing.assert_allclose(to_np(prm.B[n]), orc.B[n], rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("case", ["zipf3_j16", "zipf3_j32", "zipf4_j8"])
+def test_fiber_shared_g_is_bitwise_equal(case):
+    """Sharing g per fiber (Section 3.2) changes where g is computed, not how: results are bit-identical."""
+    import torch
+
+    import paper_2210_06014_amd as ft
+
+    name, dims, nnz, zipf, J, R, kw = [c for c in CASES if c[0] == case][0]
+    dims = [max(d // 4, 2) for d in dims]  # denser: longer fibers
+    c, v, A, B = make_problem(dims, nnz, zipf, J, R, seed=17)
+    outs = []
+    for share in (True, False):
+        for storage in ("f32", "bf16"):
+            plan, prm = gpu_setup(dims, J, R, c, v, A, B, storage=storage, fiber_share=share, **kw)
+            if share:
+                assert any(plan.mode_info(m)["fiber_shared"] for m in range(len(dims)))
+            ft.epoch(plan, prm, 1e-3, 1e-2, 1e-3, 1e-2)
+            torch.cuda.synchronize()
+            outs.append([t.clone() for t in prm.A + prm.B])
+    for a, b in zip(outs[0], outs[2]):
+        assert torch.equal(a, b)
+    for a, b in zip(outs[1], outs[3]):
+        assert torch.equal(a, b)

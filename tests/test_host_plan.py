@@ -104,3 +104,20 @@ def test_calls_before_upload_fail_cleanly():
     st = lib.ft_factor_pass(plan.handle, None, 0, 1e-3, 1e-2, None)
     assert st == 5  # FT_ERR_STATE: not uploaded
     assert b"not uploaded" in lib.ft_last_error()
+
+
+def test_fiber_counts():
+    """Mode-m fibers (Section 3.2): distinct tuples of the other indices; shared when they hold >= 4/3 elements."""
+    dims = [40, 30, 20]
+    c, _ = synth.coords(dims, 6000, 1.2, seed=8)
+    v = np.ones(c.shape[1], dtype=np.float32)
+    plan = _plan(dims, 8, 8, c, v)
+    for m in range(3):
+        others = [n for n in range(3) if n != m]
+        key = c[others[0]].astype(np.int64) * 100 + c[others[1]]
+        nf = len(np.unique(key))
+        info = plan.mode_info(m)
+        assert info["fibers"] == nf
+        assert info["fiber_shared"] == int(nf * 4 <= c.shape[1] * 3)
+    off = ft.Plan(dims, 8, 8, c, v, keep_host=True, upload=False, fiber_share=False)
+    assert all(off.mode_info(m)["fiber_shared"] == 0 for m in range(3))
