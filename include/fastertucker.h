@@ -64,8 +64,10 @@ typedef struct {
   int32_t R;                    /* core rank */
   int64_t nnz;                  /* |Omega|, 0..2^32-1 */
   int32_t chunk;                /* rows with more elements are split into chunks of this many (0: 512) */
-  int32_t fanin;                /* chunk maps folded per combine step (0: 64; at most 64 for J <= 16, 16 above) */
-  int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM */
+  int32_t fanin;                /* chunk maps folded per combine step (0 or above the maximum: 16 for
+                                   J <= 16, 8 above); a row with at most fanin maps has them applied in
+                                   sequence to its first chunk's result */
+  int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM | FT_NO_FIBER_SHARE */
 } ft_desc;
 
 /* ft_params.storage */

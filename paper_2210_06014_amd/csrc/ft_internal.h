@@ -82,6 +82,7 @@ struct ModeMeta {
   int64_t n_maps = 0;     // COMPOSE items (unpadded)
   std::vector<int64_t> level_off;  // offset of each level in the device array
   std::vector<int64_t> level_len;
+  std::vector<int64_t> level_ncomp;  // folds at the head of each level (final items follow)
   int64_t n_level_out0 = 0;        // outputs of level 0 (ping-pong buffer size)
   int64_t n_segs = 0;
   int64_t n_fibers = 0;
@@ -100,7 +101,7 @@ struct ft_plan {
   ft_desc desc{};
   int N = 0, J = 0, R = 0;
   int64_t nnz = 0;
-  int chunk = 128, fanin = 64;
+  int chunk = 512, fanin = 16;
   std::vector<ft::ModeMeta> meta;
   std::vector<ft::ModeHost> host;
   std::vector<ft::ModeDev> dev;

@@ -225,92 +225,188 @@ __global__ __launch_bounds__(256) void k_cast_bf16(const float* __restrict__ src
 // The decay is applied as an increment so that its rounding does not build
 // up over long rows.
 //
-// Per batch of 16 elements the lanes of a row first gather the C rows of all
-// 16 elements (phase 1, latency overlapped), then run the 16 dependent steps.
-// Steps past the end of an item use w = 0 and no decay, which leaves every
-// state unchanged, so the wavefront needs no divergent control flow.
+// Per batch of 16 elements the wavefront first forms g for the 16 elements of
+// each of its four items (phase 1: gathers in flight together, g = B(m) w on
+// the matrix cores), then each 16-lane group runs its item's 16 dependent
+// steps.  Steps past the end of an item use g = 0 and no decay, which leaves
+// every state unchanged, so the wavefront needs no divergent control flow.
 
-// value at byte offset `off` of a C table (uniform base + 32-bit offset: the
-// scalar-base addressing form; every table is far below 4 GB)
-template <class T>
-__device__ __forceinline__ float at_byte(const T* base, uint32_t off) {
-  return to_f(*reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off));
+// S = R/4 consecutive values at byte offset `off` of a C table (uniform base
+// + 32-bit offset: the scalar-base addressing form; every table is far below
+// 4 GB)
+template <int S, class T>
+__device__ __forceinline__ void load_s(const T* base, uint32_t off, float (&out)[S]) {
+  const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+  if constexpr (S == 2) {
+    if constexpr (std::is_same<T, float>::value) {
+      const float2 u = *reinterpret_cast<const float2*>(p);
+      out[0] = u.x;
+      out[1] = u.y;
+    } else {
+      const uint32_t u = *reinterpret_cast<const uint32_t*>(p);
+      out[0] = __uint_as_float(u << 16);
+      out[1] = __uint_as_float(u & 0xFFFF0000u);
+    }
+  } else {
+    static_assert(S % 4 == 0, "R is 8, 16 or 32");
+#pragma unroll
+    for (int h = 0; h < S / 4; ++h) {
+      const floatx4 u = load4(p + 4 * h);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) out[4 * h + k] = u[k];
+    }
+  }
 }
 
-// ixb[k]: byte offset of element (lane t)'s row in the k-th other C table
+// g = B(m) w for a tile of 16 elements on the matrix cores: K = R in S = R/4
+// steps of v_mfma_f32_16x16x4_f32.  Tile row m is one element; at step s,
+// lane 16 c + m supplies w[m][S c + s] (so that it gathers S consecutive
+// values of every C row) and lane 16 c + j supplies B(m)[j][S c + s].  The
+// result register v of lane 16 c + j is g_j of row 4 c + v (and g_{j+16} in
+// the second accumulator for J = 32).  Every caller issues the same
+// instruction sequence, so a given w yields the same bits wherever it sits.
+template <int J, int R, class T>
+__device__ __forceinline__ void load_bop(const T* __restrict__ Bm, int lw,
+                                         float (&bop)[J >= 16 ? J / 16 : 1][R / 4]) {
+  constexpr int E = J >= 16 ? J / 16 : 1;
+  constexpr int S = R / 4;
+  const int c = lw >> 4;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = (lw & 15) + 16 * e;
+#pragma unroll
+    for (int q = 0; q < S; ++q) bop[e][q] = j < J ? to_f(Bm[j * R + S * c + q]) : 0.f;
+  }
+}
+
+// w[S c .. S c + S - 1] of one element: the product of its other C rows
+// (byte offsets ib[k]), multiplied in table order
 template <int N, int R, class T>
-__device__ __forceinline__ void gather_w(const CPtrs<N, T>& cp, const int (&ixb)[N > 1 ? N - 1 : 1], int l, int t0,
-                                         int len, float (&w)[16][R >= 16 ? R / 16 : 1]) {
-  constexpr int RE = R >= 16 ? R / 16 : 1;
-  static_for<0, 16>([&](auto S) {
-    constexpr int s = decltype(S)::value;
+__device__ __forceinline__ void gather_wq(const CPtrs<N, T>& cp, const uint32_t (&ib)[N > 1 ? N - 1 : 1], int c,
+                                          float (&wq)[R / 4]) {
+  constexpr int S = R / 4;
+  const uint32_t rb = (uint32_t)(S * c * sizeof(T));
+  load_s<S, T>(cp.p[0], ib[0] + rb, wq);
+#pragma unroll
+  for (int k = 1; k < N - 1; ++k) {
+    float t[S];
+    load_s<S, T>(cp.p[k], ib[k] + rb, t);
+#pragma unroll
+    for (int q = 0; q < S; ++q) wq[q] *= t[q];
+  }
+}
+
+template <int J, int R>
+__device__ __forceinline__ void mfma_g(const float (&wq)[R / 4], const float (&bop)[J >= 16 ? J / 16 : 1][R / 4],
+                                       floatx4 (&acc)[J >= 16 ? J / 16 : 1]) {
+  constexpr int E = J >= 16 ? J / 16 : 1;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    acc[e] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < R / 4; ++q) acc[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(wq[q], bop[e][q], acc[e], 0, 0, 0);
+  }
+}
+
+// g of the 16 elements t0 .. t0 + 15 of each of the wavefront's four items:
+// tile t holds elements t0 + 4 t .. t0 + 4 t + 3 of every item, so that lane
+// 16 c + j receives g_j of its own item c.  `ot` is the item of tile row
+// l = lane % 16, i.e. item l / 4.  Elements past an item's end get w = 0.
+template <int N, int J, int R, class T>
+__device__ __forceinline__ void tile_g(const FItem& ot, int t0, int lw, const int32_t* __restrict__ idx, int64_t nnz,
+                                       const CPtrs<N, T>& cp, const float (&bop)[J >= 16 ? J / 16 : 1][R / 4],
+                                       float (&g16)[16][J >= 16 ? J / 16 : 1]) {
+  constexpr int E = J >= 16 ? J / 16 : 1;
+  constexpr int S = R / 4;
+  const int l = lw & 15;
+  static_for<0, 4>([&](auto TT) {
+    constexpr int t = decltype(TT)::value;
+    const int st = t0 + 4 * t + (l & 3);
+    const int64_t p = ot.start + min(st, max(ot.len - 1, 0));
     uint32_t ib[N - 1];
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) ib[k] = (uint32_t)bcast16i<s>(ixb[k]);
-    const bool sv = (t0 + s) < len;
+    for (int k = 0; k < N - 1; ++k)
+      ib[k] = ot.len > 0 ? (uint32_t)idx[(int64_t)k * nnz + p] * (uint32_t)(R * sizeof(T)) : 0u;
+    float wq[S];
+    gather_wq<N, R, T>(cp, ib, lw >> 4, wq);
+    if (st >= ot.len) {
 #pragma unroll
-    for (int q = 0; q < RE; ++q) {
-      const uint32_t rb = (uint32_t)((R >= 16 ? l + 16 * q : (l % R)) * sizeof(T));
-      float prod = at_byte(cp.p[0], ib[0] + rb);
-#pragma unroll
-      for (int k = 1; k < N - 1; ++k) prod *= at_byte(cp.p[k], ib[k] + rb);
-      w[s][q] = sv ? prod : 0.f;
+      for (int q = 0; q < S; ++q) wq[q] = 0.f;
     }
+    floatx4 acc[E];
+    mfma_g<J, R>(wq, bop, acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int e = 0; e < E; ++e) g16[4 * t + v][e] = acc[e][v];
   });
 }
 
-// g = B(m) w for this lane's elements j = l + 16 e; w_r comes from lane r % 16.
-template <int J, int R>
-__device__ __forceinline__ void shared_g(const float (&Bw)[J >= 16 ? J / 16 : 1][R], const float (&ws)[R >= 16 ? R / 16 : 1],
-                                         float (&g)[J >= 16 ? J / 16 : 1]) {
+// g of the 16 elements t0 .. t0 + 15 of this lane's item, read from the
+// fiber table (zero past the item's end)
+template <int J>
+__device__ __forceinline__ void fiber_tile_g(const FItem& it, int t0, int l, const int32_t* __restrict__ fid,
+                                             const float* __restrict__ gfib,
+                                             float (&g16)[16][J >= 16 ? J / 16 : 1]) {
   constexpr int E = J >= 16 ? J / 16 : 1;
-  constexpr int RE = R >= 16 ? R / 16 : 1;
-  constexpr int RK = R >= 16 ? 16 : R;
+  const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
+  const int fv = it.len > 0 ? fid[p] : 0;
+  static_for<0, 16>([&](auto S) {
+    constexpr int s = decltype(S)::value;
+    const int64_t fb = (int64_t)bcast16i<s>(fv) * J;
+    const bool sv = (t0 + s) < it.len;
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    g[e] = 0.f;
-#pragma unroll
-    for (int q = 0; q < RE; ++q) dot_bcast<RK>(g[e], ws[q], &Bw[e][16 * q]);
-  }
+    for (int e = 0; e < E; ++e) {
+      const int j = l + 16 * e;
+      g16[s][e] = (sv && j < J) ? gfib[fb + j] : 0.f;
+    }
+  });
 }
 
 // The shared intermediate of Section 3.2: g_f = B(m) w_f once per mode-m
 // fiber f (w_f = prod_{n != m} C(n)[i_n, :] is the same for every element of
-// the fiber).  Same lane layout and operation order as the per-element path,
-// so the factor pass gives the same bits either way.  16 fibers per group.
+// the fiber).  Same tiles as the per-element path, so the factor pass gives
+// the same bits either way.  kFiberTiles tiles of 16 fibers per wavefront,
+// their gathers issued together.
+constexpr int kFiberTiles = 4;
+
 template <int N, int J, int R, class T>
 __global__ __launch_bounds__(256) void k_fiber_g(const int32_t* __restrict__ fib_idx, int64_t nfib, CPtrs<N, T> cp,
                                                  const T* __restrict__ Bm, float* __restrict__ gfib) {
   constexpr int E = J >= 16 ? J / 16 : 1;
-  constexpr int RE = R >= 16 ? R / 16 : 1;
-  const int l = threadIdx.x & 15;
-  const int64_t f0 = ((int64_t)blockIdx.x * 16 + (threadIdx.x >> 4)) * 16;
-  float Bw[E][R];
+  constexpr int S = R / 4;
+  constexpr int TW = kFiberTiles;
+  const int lw = threadIdx.x & 63, m = lw & 15, c = lw >> 4;
+  const int64_t f0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * TW;
+  if (f0 >= nfib) return;  // whole wavefront
+  float bop[E][S];
+  load_bop<J, R, T>(Bm, lw, bop);
+  uint32_t ib[TW][N - 1];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int j = l + 16 * e;
+  for (int t = 0; t < TW; ++t) {
+    const int64_t f = min(f0 + 16 * t + m, nfib - 1);
 #pragma unroll
-    for (int r = 0; r < R; ++r) Bw[e][r] = j < J ? to_f(Bm[j * R + r]) : 0.f;
+    for (int k = 0; k < N - 1; ++k) ib[t][k] = (uint32_t)fib_idx[(int64_t)k * nfib + f] * (uint32_t)(R * sizeof(T));
   }
-  const int len = (int)max<int64_t>(0, min<int64_t>(16, nfib - f0));
-  const int64_t f = min(f0 + l, nfib - 1);
-  int ixb[N - 1];
+  float wq[TW][S];
 #pragma unroll
-  for (int k = 0; k < N - 1; ++k) ixb[k] = len > 0 ? fib_idx[(int64_t)k * nfib + f] * (int)(R * sizeof(T)) : 0;
-  float w[16][RE];
-  gather_w<N, R, T>(cp, ixb, l, 0, len, w);
-  static_for<0, 16>([&](auto S) {
-    constexpr int s = decltype(S)::value;
-    float g[E];
-    shared_g<J, R>(Bw, w[s], g);
-    if (s < len) {
+  for (int t = 0; t < TW; ++t) gather_wq<N, R, T>(cp, ib[t], c, wq[t]);
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int j = l + 16 * e;
-        if (j < J) gfib[(f0 + s) * J + j] = g[e];
+  for (int t = 0; t < TW; ++t) {
+    floatx4 acc[E];
+    mfma_g<J, R>(wq[t], bop, acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t fo = f0 + 16 * t + 4 * c + v;
+      if (fo < nfib) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int j = m + 16 * e;
+          if (j < J) gfib[fo * J + j] = acc[e][v];
+        }
       }
     }
-  });
+  }
 }
 
 template <int N, int J, int R, class T, bool FIB>
@@ -321,23 +417,21 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
                                                       float* __restrict__ hvec, float lr, float c1,
                                                       const int32_t* __restrict__ fid, const float* __restrict__ gfib) {
   constexpr int E = J >= 16 ? J / 16 : 1;
-  constexpr int RE = R >= 16 ? R / 16 : 1;
-  const int l = threadIdx.x & 15;
-  float Bw[E][R];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int j = l + 16 * e;
-#pragma unroll
-    for (int r = 0; r < R; ++r) Bw[e][r] = (!FIB && j < J) ? to_f(Bm[j * R + r]) : 0.f;
-  }
+  const int lw = threadIdx.x & 63, l = lw & 15;
+  float bop[E][R / 4];
+  if constexpr (!FIB) load_bop<J, R, T>(Bm, lw, bop);
   // Persistent groups: the four groups of a wavefront take four consecutive
   // items (similar lengths, the lists are sorted) and then stride by the grid,
   // so B(m) is loaded once per group.  The trip count is wave-uniform.
   const int64_t G = (int64_t)gridDim.x * 16;
   for (int64_t base = (int64_t)blockIdx.x * 16 + ((threadIdx.x >> 6) << 2); base < n_items; base += G) {
   const int64_t gid = base + ((threadIdx.x >> 4) & 3);
-  FItem it{0, 0, 0, 0, 0};
+  FItem it{0, 0, 0, 0, 0}, ot{0, 0, 0, 0, 0};
   if (gid < n_items) it = items[gid];
+  if constexpr (!FIB) {
+    const int64_t og = base + (l >> 2);  // item of this lane's tile rows
+    if (og < n_items) ot = items[og];
+  }
   // The row is carried in FP64 registers and rounded to FP32 once when
   // stored: the decay step lr*lam*a is about a hundred ulps of a, nearly the
   // same every step, so FP32 rounding of the running state would accumulate
@@ -356,36 +450,17 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
     // steps are neutralised below (w = 0, no decay)
     const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
     const float xv = it.len > 0 ? val[p] : 0.f;
-    // phase 1: w of the 16 elements (or, with fibers, their precomputed g)
-    float w[16][FIB ? E : RE];
-    if constexpr (FIB) {
-      const int fv = it.len > 0 ? fid[p] : 0;
-      static_for<0, 16>([&](auto S) {
-        constexpr int s = decltype(S)::value;
-        const int64_t fb = (int64_t)bcast16i<s>(fv) * J;
-        const bool sv = (t0 + s) < it.len;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int j = l + 16 * e;
-          w[s][e] = (sv && j < J) ? gfib[fb + j] : 0.f;
-        }
-      });
-    } else {
-      int ix[N - 1];
-#pragma unroll
-      for (int k = 0; k < N - 1; ++k)
-        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (int)(R * sizeof(T)) : 0;
-      gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
-    }
+    // phase 1: g of the 16 elements (matrix-core tiles, or the fiber table)
+    float g16[16][E];
+    if constexpr (FIB)
+      fiber_tile_g<J>(it, t0, l, fid, gfib, g16);
+    else
+      tile_g<N, J, R, T>(ot, t0, lw, idx, nnz, cp, bop, g16);
     static_for<0, 16>([&](auto S) {
       constexpr int s = decltype(S)::value;
       float g[E];
-      if constexpr (FIB) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) g[e] = w[s][e];
-      } else {
-        shared_g<J, R>(Bw, w[s], g);
-      }
+      for (int e = 0; e < E; ++e) g[e] = g16[s][e];
       float pr = 0.f;
 #pragma unroll
       for (int e = 0; e < E; ++e) pr = fmaf((float)a[e], g[e], pr);
@@ -430,24 +505,22 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
                                                         double rho, const int32_t* __restrict__ fid,
                                                         const float* __restrict__ gfib) {
   constexpr int E = J >= 16 ? J / 16 : 1;
-  constexpr int RE = R >= 16 ? R / 16 : 1;
   constexpr int MS = J * J + J;
-  const int l = threadIdx.x & 15;
-  float Bw[E][R];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int j = l + 16 * e;
-#pragma unroll
-    for (int r = 0; r < R; ++r) Bw[e][r] = (!FIB && j < J) ? to_f(Bm[j * R + r]) : 0.f;
-  }
+  const int lw = threadIdx.x & 63, l = lw & 15;
+  float bop[E][R / 4];
+  if constexpr (!FIB) load_bop<J, R, T>(Bm, lw, bop);
   // Persistent groups: the four groups of a wavefront take four consecutive
   // items (similar lengths, the lists are sorted) and then stride by the grid,
   // so B(m) is loaded once per group.  The trip count is wave-uniform.
   const int64_t G = (int64_t)gridDim.x * 16;
   for (int64_t base = (int64_t)blockIdx.x * 16 + ((threadIdx.x >> 6) << 2); base < n_items; base += G) {
   const int64_t gid = base + ((threadIdx.x >> 4) & 3);
-  FItem it{0, 0, 0, 0, 0};
+  FItem it{0, 0, 0, 0, 0}, ot{0, 0, 0, 0, 0};
   if (gid < n_items) it = items[gid];
+  if constexpr (!FIB) {
+    const int64_t og = base + (l >> 2);  // item of this lane's tile rows
+    if (og < n_items) ot = items[og];
+  }
   float Nc[E][J];
   float v[E];
 #pragma unroll
@@ -464,36 +537,17 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
     // steps are neutralised below (w = 0, no decay)
     const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
     const float xv = it.len > 0 ? val[p] : 0.f;
-    // phase 1: w of the 16 elements (or, with fibers, their precomputed g)
-    float w[16][FIB ? E : RE];
-    if constexpr (FIB) {
-      const int fv = it.len > 0 ? fid[p] : 0;
-      static_for<0, 16>([&](auto S) {
-        constexpr int s = decltype(S)::value;
-        const int64_t fb = (int64_t)bcast16i<s>(fv) * J;
-        const bool sv = (t0 + s) < it.len;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int j = l + 16 * e;
-          w[s][e] = (sv && j < J) ? gfib[fb + j] : 0.f;
-        }
-      });
-    } else {
-      int ix[N - 1];
-#pragma unroll
-      for (int k = 0; k < N - 1; ++k)
-        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (int)(R * sizeof(T)) : 0;
-      gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
-    }
+    // phase 1: g of the 16 elements (matrix-core tiles, or the fiber table)
+    float g16[16][E];
+    if constexpr (FIB)
+      fiber_tile_g<J>(it, t0, l, fid, gfib, g16);
+    else
+      tile_g<N, J, R, T>(ot, t0, lw, idx, nnz, cp, bop, g16);
     static_for<0, 16>([&](auto S) {
       constexpr int s = decltype(S)::value;
       float g[E];
-      if constexpr (FIB) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) g[e] = w[s][e];
-      } else {
-        shared_g<J, R>(Bw, w[s], g);
-      }
+      for (int e = 0; e < E; ++e) g[e] = g16[s][e];
       constexpr int JK = J >= 16 ? 16 : J;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -539,17 +593,16 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
 // LDS (fixed bracketing: pairs (0,1), (2,3), ... then (0,2), ... so that a
 // later map is always applied after an earlier one):
 //   (s2, N2, v2) o (s1, N1, v1) = (s1 s2, N1 + N2 + N2 N1, s2 (v1 + N2 v1) + v2),
-// with s = rho^length kept in FP64.  The last fold of a row applies the map to
-// the row's head vector (the state after its first chunk) and writes A(m).
+// with s = rho^length kept in FP64.  Only rows with more maps than the last
+// fold takes in sequence (below) pass through here.
 template <int J>
 constexpr int combine_fanin() {
-  return J <= 16 ? 64 : 16;  // maps held in LDS by one workgroup
+  return J <= 16 ? 16 : 8;  // maps held in LDS by one workgroup
 }
 
 template <int J>
 __global__ __launch_bounds__(256) void k_combine(const CItem* __restrict__ items, float* __restrict__ maps,
-                                                 double* __restrict__ map_scale, const float* __restrict__ hvec,
-                                                 float* __restrict__ Am) {
+                                                 double* __restrict__ map_scale) {
   constexpr int MS = J * J + J;
   constexpr int F = combine_fanin<J>();
   constexpr int RMAX = (F / 2 * J * J + 255) / 256;  // matrix entries per thread at the widest level
@@ -619,16 +672,88 @@ __global__ __launch_bounds__(256) void k_combine(const CItem* __restrict__ items
     }
     __syncthreads();
   }
-  if (it.out_off >= 0) {
-    float* dst = maps + it.out_off * MS;
-    for (int k = t; k < MS; k += 256) dst[k] = buf[k];
-    if (t == 0) map_scale[it.out_off] = sc[0];
-  } else if (t < J) {
-    const float* a0 = hvec + (int64_t)it.heavy * J;
-    float acc = 0.f;
+  float* dst = maps + it.out_off * MS;
+  for (int k = t; k < MS; k += 256) dst[k] = buf[k];
+  if (t == 0) map_scale[it.out_off] = sc[0];
+}
+
+// Last fold of a heavy row: its remaining maps, earliest first, applied to
+// the head vector (the row's state after its first chunk),
+//     a <- s (a + N a) + v,
+// J^2 work per map where composing two maps costs J^3.  One 16-lane group
+// per row; lane i holds a_i in FP64 and row i of the maps in flight (D of
+// them, loaded ahead of the dependent chain).  Rows of a wavefront have
+// similar map counts (the list is sorted by count); steps past a row's count
+// leave it unchanged.
+template <int J>
+__global__ __launch_bounds__(256) void k_combine_final(const CItem* __restrict__ items, int64_t n_items,
+                                                       const float* __restrict__ maps,
+                                                       const double* __restrict__ map_scale,
+                                                       const float* __restrict__ hvec, float* __restrict__ Am) {
+  constexpr int E = J >= 16 ? J / 16 : 1;
+  constexpr int K = J >= 16 ? 16 : J;
+  constexpr int MS = J * J + J;
+  constexpr int D = J >= 32 ? 2 : 4;
+  const int l = threadIdx.x & 15;
+  const int64_t gid = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  CItem it{0, 0, 0, 0, 0, 0};
+  if (gid < n_items) it = items[gid];
+  double a[E];
 #pragma unroll
-    for (int q = 0; q < J; ++q) acc = fmaf(buf[q * J + t], a0[q], acc);
-    Am[(int64_t)it.row * J + t] = (float)(sc[0] * ((double)a0[t] + (double)acc)) + buf[J * J + t];
+  for (int e = 0; e < E; ++e) {
+    const int j = l + 16 * e;
+    a[e] = (it.count > 0 && j < J) ? (double)hvec[(int64_t)it.heavy * J + j] : 0.0;
+  }
+  int maxc = it.count;
+  maxc = max(maxc, __shfl_xor(maxc, 16));
+  maxc = max(maxc, __shfl_xor(maxc, 32));
+  // row i = l + 16 e of map k (entry (i, q) at q J + i); lanes past J (J = 8)
+  // read row J - 1 and discard it.  Past the row's count: its last map.
+  auto load = [&](int k, float (&Nr)[E][J], float (&v)[E], double& sc) {
+    const int64_t slot = it.in_off + min(k, max(it.count - 1, 0));
+    const float* mp = maps + slot * MS;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = min(l + 16 * e, J - 1);
+#pragma unroll
+      for (int q = 0; q < J; ++q) Nr[e][q] = mp[q * J + i];
+      v[e] = mp[J * J + i];
+    }
+    sc = map_scale[slot];
+  };
+  float Nq[D][E][J], vq[D][E];
+  double sq[D];
+  static_for<0, D>([&](auto S) { load(decltype(S)::value, Nq[decltype(S)::value], vq[decltype(S)::value],
+                                      sq[decltype(S)::value]); });
+  for (int k0 = 0; k0 < maxc; k0 += D) {
+    static_for<0, D>([&](auto S) {
+      constexpr int d = decltype(S)::value;
+      const int k = k0 + d;
+      if (k < maxc) {
+        float af[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) af[e] = (float)a[e];
+        float acc[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          acc[e] = 0.f;
+#pragma unroll
+          for (int e2 = 0; e2 < E; ++e2) dot_bcast<K>(acc[e], af[e2], &Nq[d][e][16 * e2]);
+        }
+        if (k < it.count) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) a[e] = sq[d] * (a[e] + (double)acc[e]) + (double)vq[d][e];
+        }
+        load(k + D, Nq[d], vq[d], sq[d]);
+      }
+    });
+  }
+  if (it.count > 0) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = l + 16 * e;
+      if (j < J) Am[(int64_t)it.row * J + j] = (float)a[e];
+    }
   }
 }
 
@@ -996,9 +1121,10 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr,
   const float flr = (float)lr, c1 = (float)(-lr * lam), gp = (float)(lr / rho);
   if (FIB) {
     KTimer tm(P, FT_K_FIBER_G, s);
-    const int64_t groups = (M.n_fibers + 15) / 16;
-    hipLaunchKernelGGL((k_fiber_g<N, J, R, T>), dim3((unsigned)((groups + 15) / 16)), dim3(256), 0, s, D.fib_idx,
-                       M.n_fibers, cp, Bm, P->gfib);
+    // kFiberTiles tiles of 16 fibers per wavefront, four wavefronts per workgroup
+    const int64_t per_block = 4 * 16 * kFiberTiles;
+    hipLaunchKernelGGL((k_fiber_g<N, J, R, T>), dim3((unsigned)((M.n_fibers + per_block - 1) / per_block)), dim3(256),
+                       0, s, D.fib_idx, M.n_fibers, cp, Bm, P->gfib);
   }
   if (M.n_compose > 0) {
     KTimer tm(P, FT_K_FACTOR_COMPOSE, s);
@@ -1015,8 +1141,13 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr,
   }
   for (size_t L = 0; L < M.level_len.size(); ++L) {
     KTimer tm(P, FT_K_COMBINE, s);
-    hipLaunchKernelGGL((k_combine<J>), dim3((unsigned)M.level_len[L]), dim3(256), 0, s, D.levels + M.level_off[L],
-                       P->maps, P->map_scale, P->hvec, p->A[m]);
+    const int64_t nc = M.level_ncomp[L], nf = M.level_len[L] - nc;
+    if (nc > 0)
+      hipLaunchKernelGGL((k_combine<J>), dim3((unsigned)nc), dim3(256), 0, s, D.levels + M.level_off[L], P->maps,
+                         P->map_scale);
+    if (nf > 0)
+      hipLaunchKernelGGL((k_combine_final<J>), dim3((unsigned)((nf + 15) / 16)), dim3(256), 0, s,
+                         D.levels + M.level_off[L] + nc, nf, P->maps, P->map_scale, P->hvec, p->A[m]);
   }
   return hipGetLastError();
 }

@@ -202,8 +202,12 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   H.apply.insert(H.apply.end(), light.begin(), light.end());
   pad4(H.apply, ITEM_LIGHT);
 
-  // combine levels: fold each heavy row's maps `fanin` at a time until one remains
-  const int64_t fan = P->fanin;
+  // combine levels: a heavy row whose maps number at most fanin has them
+  // applied in sequence to its head vector (a final item); a longer row first
+  // has groups of `fanin` consecutive maps folded into one, level by level.
+  // Each level lists its folds first, then its final items by descending map
+  // count (similar counts share a wavefront).
+  const int64_t fan = P->fanin, fin = P->fanin;
   std::vector<int64_t> cur_off(heavy_base), cur_n(heavy_nmaps);
   int64_t region_base[2] = {0, n_maps};
   int level = 0;
@@ -211,14 +215,14 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   std::vector<int64_t> active;
   for (int64_t h = 0; h < n_heavy; ++h) active.push_back(h);
   while (!active.empty()) {
-    std::vector<CItem> items;
+    std::vector<CItem> items, finals;
     std::vector<int64_t> next;
     int64_t out_next = 0;
     int dst = (level + 1) & 1;
     for (int64_t h : active) {
       int64_t n = cur_n[h], off = cur_off[h];
-      if (n <= fan) {
-        items.push_back(CItem{off, -1, (int32_t)n, (int32_t)heavy_rows[h], (int32_t)h, 0});
+      if (n <= fin) {
+        finals.push_back(CItem{off, -1, (int32_t)n, (int32_t)heavy_rows[h], (int32_t)h, 0});
         continue;
       }
       int64_t groups = (n + fan - 1) / fan;
@@ -233,6 +237,9 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
     }
     if (level == 0) out0 = out_next;
     if (out_next > (dst == 1 ? INT64_MAX : n_maps)) return fail(FT_ERR_STATE, "combine plan overflow");
+    std::stable_sort(finals.begin(), finals.end(), [](const CItem& x, const CItem& y) { return x.count > y.count; });
+    M.level_ncomp.push_back((int64_t)items.size());
+    items.insert(items.end(), finals.begin(), finals.end());
     H.levels.push_back(std::move(items));
     active.swap(next);
     ++level;
@@ -334,7 +341,7 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
   P->R = d->R;
   P->nnz = nnz;
   P->chunk = d->chunk ? d->chunk : 512;
-  P->fanin = std::min(d->fanin ? d->fanin : 64, max_fanin(d->J[0]));
+  P->fanin = std::min(d->fanin ? d->fanin : max_fanin(d->J[0]), max_fanin(d->J[0]));
   try {
     P->meta.resize(N);
     P->host.resize(N);
