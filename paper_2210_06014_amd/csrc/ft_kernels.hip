@@ -225,187 +225,106 @@ __global__ __launch_bounds__(256) void k_cast_bf16(const float* __restrict__ src
 // The decay is applied as an increment so that its rounding does not build
 // up over long rows.
 //
-// Per batch of 16 elements the wavefront first forms g for the 16 elements of
-// each of its four items (phase 1: gathers in flight together, g = B(m) w on
-// the matrix cores), then each 16-lane group runs its item's 16 dependent
-// steps.  Steps past the end of an item use g = 0 and no decay, which leaves
-// every state unchanged, so the wavefront needs no divergent control flow.
+// Per batch of 16 elements the lanes of a row first gather the C rows of all
+// 16 elements (phase 1, latency overlapped), then run the 16 dependent steps.
+// Steps past the end of an item use w = 0 and no decay, which leaves every
+// state unchanged, so the wavefront needs no divergent control flow.
 
-// S = R/4 consecutive values at byte offset `off` of a C table (uniform base
-// + 32-bit offset: the scalar-base addressing form; every table is far below
-// 4 GB)
-template <int S, class T>
-__device__ __forceinline__ void load_s(const T* base, uint32_t off, float (&out)[S]) {
-  const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
-  if constexpr (S == 2) {
-    if constexpr (std::is_same<T, float>::value) {
-      const float2 u = *reinterpret_cast<const float2*>(p);
-      out[0] = u.x;
-      out[1] = u.y;
-    } else {
-      const uint32_t u = *reinterpret_cast<const uint32_t*>(p);
-      out[0] = __uint_as_float(u << 16);
-      out[1] = __uint_as_float(u & 0xFFFF0000u);
-    }
-  } else {
-    static_assert(S % 4 == 0, "R is 8, 16 or 32");
-#pragma unroll
-    for (int h = 0; h < S / 4; ++h) {
-      const floatx4 u = load4(p + 4 * h);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) out[4 * h + k] = u[k];
-    }
-  }
+// value at byte offset `off` of a C table (uniform base + 32-bit offset: the
+// scalar-base addressing form; every table is far below 4 GB)
+template <class T>
+__device__ __forceinline__ float at_byte(const T* base, uint32_t off) {
+  return to_f(*reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off));
 }
 
-// g = B(m) w for a tile of 16 elements on the matrix cores: K = R in S = R/4
-// steps of v_mfma_f32_16x16x4_f32.  Tile row m is one element; at step s,
-// lane 16 c + m supplies w[m][S c + s] (so that it gathers S consecutive
-// values of every C row) and lane 16 c + j supplies B(m)[j][S c + s].  The
-// result register v of lane 16 c + j is g_j of row 4 c + v (and g_{j+16} in
-// the second accumulator for J = 32).  Every caller issues the same
-// instruction sequence, so a given w yields the same bits wherever it sits.
-template <int J, int R, class T>
-__device__ __forceinline__ void load_bop(const T* __restrict__ Bm, int lw,
-                                         float (&bop)[J >= 16 ? J / 16 : 1][R / 4]) {
-  constexpr int E = J >= 16 ? J / 16 : 1;
-  constexpr int S = R / 4;
-  const int c = lw >> 4;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int j = (lw & 15) + 16 * e;
-#pragma unroll
-    for (int q = 0; q < S; ++q) bop[e][q] = j < J ? to_f(Bm[j * R + S * c + q]) : 0.f;
-  }
-}
-
-// w[S c .. S c + S - 1] of one element: the product of its other C rows
-// (byte offsets ib[k]), multiplied in table order
+// ixb[k]: byte offset of element (lane t)'s row in the k-th other C table
 template <int N, int R, class T>
-__device__ __forceinline__ void gather_wq(const CPtrs<N, T>& cp, const uint32_t (&ib)[N > 1 ? N - 1 : 1], int c,
-                                          float (&wq)[R / 4]) {
-  constexpr int S = R / 4;
-  const uint32_t rb = (uint32_t)(S * c * sizeof(T));
-  load_s<S, T>(cp.p[0], ib[0] + rb, wq);
-#pragma unroll
-  for (int k = 1; k < N - 1; ++k) {
-    float t[S];
-    load_s<S, T>(cp.p[k], ib[k] + rb, t);
-#pragma unroll
-    for (int q = 0; q < S; ++q) wq[q] *= t[q];
-  }
-}
-
-template <int J, int R>
-__device__ __forceinline__ void mfma_g(const float (&wq)[R / 4], const float (&bop)[J >= 16 ? J / 16 : 1][R / 4],
-                                       floatx4 (&acc)[J >= 16 ? J / 16 : 1]) {
-  constexpr int E = J >= 16 ? J / 16 : 1;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    acc[e] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int q = 0; q < R / 4; ++q) acc[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(wq[q], bop[e][q], acc[e], 0, 0, 0);
-  }
-}
-
-// g of the 16 elements t0 .. t0 + 15 of each of the wavefront's four items:
-// tile t holds elements t0 + 4 t .. t0 + 4 t + 3 of every item, so that lane
-// 16 c + j receives g_j of its own item c.  `ot` is the item of tile row
-// l = lane % 16, i.e. item l / 4.  Elements past an item's end get w = 0.
-template <int N, int J, int R, class T>
-__device__ __forceinline__ void tile_g(const FItem& ot, int t0, int lw, const int32_t* __restrict__ idx, int64_t nnz,
-                                       const CPtrs<N, T>& cp, const float (&bop)[J >= 16 ? J / 16 : 1][R / 4],
-                                       float (&g16)[16][J >= 16 ? J / 16 : 1]) {
-  constexpr int E = J >= 16 ? J / 16 : 1;
-  constexpr int S = R / 4;
-  const int l = lw & 15;
-  static_for<0, 4>([&](auto TT) {
-    constexpr int t = decltype(TT)::value;
-    const int st = t0 + 4 * t + (l & 3);
-    const int64_t p = ot.start + min(st, max(ot.len - 1, 0));
-    uint32_t ib[N - 1];
-#pragma unroll
-    for (int k = 0; k < N - 1; ++k)
-      ib[k] = ot.len > 0 ? (uint32_t)idx[(int64_t)k * nnz + p] * (uint32_t)(R * sizeof(T)) : 0u;
-    float wq[S];
-    gather_wq<N, R, T>(cp, ib, lw >> 4, wq);
-    if (st >= ot.len) {
-#pragma unroll
-      for (int q = 0; q < S; ++q) wq[q] = 0.f;
-    }
-    floatx4 acc[E];
-    mfma_g<J, R>(wq, bop, acc);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int e = 0; e < E; ++e) g16[4 * t + v][e] = acc[e][v];
-  });
-}
-
-// g of the 16 elements t0 .. t0 + 15 of this lane's item, read from the
-// fiber table (zero past the item's end)
-template <int J>
-__device__ __forceinline__ void fiber_tile_g(const FItem& it, int t0, int l, const int32_t* __restrict__ fid,
-                                             const float* __restrict__ gfib,
-                                             float (&g16)[16][J >= 16 ? J / 16 : 1]) {
-  constexpr int E = J >= 16 ? J / 16 : 1;
-  const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
-  const int fv = it.len > 0 ? fid[p] : 0;
+__device__ __forceinline__ void gather_w(const CPtrs<N, T>& cp, const int (&ixb)[N > 1 ? N - 1 : 1], int l, int t0,
+                                         int len, float (&w)[16][R >= 16 ? R / 16 : 1]) {
+  constexpr int RE = R >= 16 ? R / 16 : 1;
   static_for<0, 16>([&](auto S) {
     constexpr int s = decltype(S)::value;
-    const int64_t fb = (int64_t)bcast16i<s>(fv) * J;
-    const bool sv = (t0 + s) < it.len;
+    uint32_t ib[N - 1];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int j = l + 16 * e;
-      g16[s][e] = (sv && j < J) ? gfib[fb + j] : 0.f;
+    for (int k = 0; k < N - 1; ++k) ib[k] = (uint32_t)bcast16i<s>(ixb[k]);
+    const bool sv = (t0 + s) < len;
+#pragma unroll
+    for (int q = 0; q < RE; ++q) {
+      const uint32_t rb = (uint32_t)((R >= 16 ? l + 16 * q : (l % R)) * sizeof(T));
+      float prod = at_byte(cp.p[0], ib[0] + rb);
+#pragma unroll
+      for (int k = 1; k < N - 1; ++k) prod *= at_byte(cp.p[k], ib[k] + rb);
+      w[s][q] = sv ? prod : 0.f;
     }
   });
+}
+
+// g = B(m) w for this lane's elements j = l + 16 e; w_r comes from lane r % 16.
+template <int J, int R>
+__device__ __forceinline__ void shared_g(const float (&Bw)[J >= 16 ? J / 16 : 1][R], const float (&ws)[R >= 16 ? R / 16 : 1],
+                                         float (&g)[J >= 16 ? J / 16 : 1]) {
+  constexpr int E = J >= 16 ? J / 16 : 1;
+  constexpr int RE = R >= 16 ? R / 16 : 1;
+  constexpr int RK = R >= 16 ? 16 : R;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    g[e] = 0.f;
+#pragma unroll
+    for (int q = 0; q < RE; ++q) dot_bcast<RK>(g[e], ws[q], &Bw[e][16 * q]);
+  }
 }
 
 // The shared intermediate of Section 3.2: g_f = B(m) w_f once per mode-m
 // fiber f (w_f = prod_{n != m} C(n)[i_n, :] is the same for every element of
-// the fiber).  Same tiles as the per-element path, so the factor pass gives
-// the same bits either way.  kFiberTiles tiles of 16 fibers per wavefront,
-// their gathers issued together.
-constexpr int kFiberTiles = 4;
+// the fiber).  Same lane layout and operation order as the per-element path,
+// so the factor pass gives the same bits either way.  Each 16-lane group takes
+// kFiberBatches batches of 16 fibers and issues all their gathers first.
+constexpr int kFiberBatches = 2;
 
 template <int N, int J, int R, class T>
 __global__ __launch_bounds__(256) void k_fiber_g(const int32_t* __restrict__ fib_idx, int64_t nfib, CPtrs<N, T> cp,
                                                  const T* __restrict__ Bm, float* __restrict__ gfib) {
   constexpr int E = J >= 16 ? J / 16 : 1;
-  constexpr int S = R / 4;
-  constexpr int TW = kFiberTiles;
-  const int lw = threadIdx.x & 63, m = lw & 15, c = lw >> 4;
-  const int64_t f0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * TW;
-  if (f0 >= nfib) return;  // whole wavefront
-  float bop[E][S];
-  load_bop<J, R, T>(Bm, lw, bop);
-  uint32_t ib[TW][N - 1];
+  constexpr int RE = R >= 16 ? R / 16 : 1;
+  constexpr int FB = kFiberBatches;
+  const int l = threadIdx.x & 15;
+  const int64_t f00 = ((int64_t)blockIdx.x * 16 + (threadIdx.x >> 4)) * 16 * FB;
+  float Bw[E][R];
 #pragma unroll
-  for (int t = 0; t < TW; ++t) {
-    const int64_t f = min(f0 + 16 * t + m, nfib - 1);
+  for (int e = 0; e < E; ++e) {
+    const int j = l + 16 * e;
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) ib[t][k] = (uint32_t)fib_idx[(int64_t)k * nfib + f] * (uint32_t)(R * sizeof(T));
+    for (int r = 0; r < R; ++r) Bw[e][r] = j < J ? to_f(Bm[j * R + r]) : 0.f;
   }
-  float wq[TW][S];
+  int len[FB];
+  int ixb[FB][N - 1];
 #pragma unroll
-  for (int t = 0; t < TW; ++t) gather_wq<N, R, T>(cp, ib[t], c, wq[t]);
+  for (int b = 0; b < FB; ++b) {
+    const int64_t f0 = f00 + 16 * b;
+    len[b] = (int)max<int64_t>(0, min<int64_t>(16, nfib - f0));
+    const int64_t f = min(f0 + l, nfib - 1);
 #pragma unroll
-  for (int t = 0; t < TW; ++t) {
-    floatx4 acc[E];
-    mfma_g<J, R>(wq[t], bop, acc);
+    for (int k = 0; k < N - 1; ++k)
+      ixb[b][k] = len[b] > 0 ? fib_idx[(int64_t)k * nfib + f] * (int)(R * sizeof(T)) : 0;
+  }
+  float w[FB][16][RE];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t fo = f0 + 16 * t + 4 * c + v;
-      if (fo < nfib) {
+  for (int b = 0; b < FB; ++b) gather_w<N, R, T>(cp, ixb[b], l, 0, len[b], w[b]);
+#pragma unroll
+  for (int b = 0; b < FB; ++b) {
+    const int64_t f0 = f00 + 16 * b;
+    static_for<0, 16>([&](auto S) {
+      constexpr int s = decltype(S)::value;
+      float g[E];
+      shared_g<J, R>(Bw, w[b][s], g);
+      if (s < len[b]) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          const int j = m + 16 * e;
-          if (j < J) gfib[fo * J + j] = acc[e][v];
+          const int j = l + 16 * e;
+          if (j < J) gfib[(f0 + s) * J + j] = g[e];
         }
       }
-    }
+    });
   }
 }
 
@@ -417,21 +336,23 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
                                                       float* __restrict__ hvec, float lr, float c1,
                                                       const int32_t* __restrict__ fid, const float* __restrict__ gfib) {
   constexpr int E = J >= 16 ? J / 16 : 1;
-  const int lw = threadIdx.x & 63, l = lw & 15;
-  float bop[E][R / 4];
-  if constexpr (!FIB) load_bop<J, R, T>(Bm, lw, bop);
+  constexpr int RE = R >= 16 ? R / 16 : 1;
+  const int l = threadIdx.x & 15;
+  float Bw[E][R];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = l + 16 * e;
+#pragma unroll
+    for (int r = 0; r < R; ++r) Bw[e][r] = (!FIB && j < J) ? to_f(Bm[j * R + r]) : 0.f;
+  }
   // Persistent groups: the four groups of a wavefront take four consecutive
   // items (similar lengths, the lists are sorted) and then stride by the grid,
   // so B(m) is loaded once per group.  The trip count is wave-uniform.
   const int64_t G = (int64_t)gridDim.x * 16;
   for (int64_t base = (int64_t)blockIdx.x * 16 + ((threadIdx.x >> 6) << 2); base < n_items; base += G) {
   const int64_t gid = base + ((threadIdx.x >> 4) & 3);
-  FItem it{0, 0, 0, 0, 0}, ot{0, 0, 0, 0, 0};
+  FItem it{0, 0, 0, 0, 0};
   if (gid < n_items) it = items[gid];
-  if constexpr (!FIB) {
-    const int64_t og = base + (l >> 2);  // item of this lane's tile rows
-    if (og < n_items) ot = items[og];
-  }
   // The row is carried in FP64 registers and rounded to FP32 once when
   // stored: the decay step lr*lam*a is about a hundred ulps of a, nearly the
   // same every step, so FP32 rounding of the running state would accumulate
@@ -450,17 +371,39 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
     // steps are neutralised below (w = 0, no decay)
     const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
     const float xv = it.len > 0 ? val[p] : 0.f;
-    // phase 1: g of the 16 elements (matrix-core tiles, or the fiber table)
-    float g16[16][E];
-    if constexpr (FIB)
-      fiber_tile_g<J>(it, t0, l, fid, gfib, g16);
-    else
-      tile_g<N, J, R, T>(ot, t0, lw, idx, nnz, cp, bop, g16);
+    // phase 1: w of the 16 elements (or, with fibers, their precomputed g)
+    float w[16][FIB ? E : RE];
+    if constexpr (FIB) {
+      const int fv = it.len > 0 ? fid[p] : 0;
+      static_for<0, 16>([&](auto S) {
+        constexpr int s = decltype(S)::value;
+        const int64_t fb = (int64_t)bcast16i<s>(fv) * J;
+        const bool sv = (t0 + s) < it.len;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          // unconditional load (fv is a valid fiber, the column clamped) so
+          // that all 16 loads are in flight together; masked afterwards
+          const int j = l + 16 * e;
+          const float gv = gfib[fb + min(j, J - 1)];
+          w[s][e] = (sv && j < J) ? gv : 0.f;
+        }
+      });
+    } else {
+      int ix[N - 1];
+#pragma unroll
+      for (int k = 0; k < N - 1; ++k)
+        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (int)(R * sizeof(T)) : 0;
+      gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
+    }
     static_for<0, 16>([&](auto S) {
       constexpr int s = decltype(S)::value;
       float g[E];
+      if constexpr (FIB) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) g[e] = g16[s][e];
+        for (int e = 0; e < E; ++e) g[e] = w[s][e];
+      } else {
+        shared_g<J, R>(Bw, w[s], g);
+      }
       float pr = 0.f;
 #pragma unroll
       for (int e = 0; e < E; ++e) pr = fmaf((float)a[e], g[e], pr);
@@ -505,22 +448,24 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
                                                         double rho, const int32_t* __restrict__ fid,
                                                         const float* __restrict__ gfib) {
   constexpr int E = J >= 16 ? J / 16 : 1;
+  constexpr int RE = R >= 16 ? R / 16 : 1;
   constexpr int MS = J * J + J;
-  const int lw = threadIdx.x & 63, l = lw & 15;
-  float bop[E][R / 4];
-  if constexpr (!FIB) load_bop<J, R, T>(Bm, lw, bop);
+  const int l = threadIdx.x & 15;
+  float Bw[E][R];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = l + 16 * e;
+#pragma unroll
+    for (int r = 0; r < R; ++r) Bw[e][r] = (!FIB && j < J) ? to_f(Bm[j * R + r]) : 0.f;
+  }
   // Persistent groups: the four groups of a wavefront take four consecutive
   // items (similar lengths, the lists are sorted) and then stride by the grid,
   // so B(m) is loaded once per group.  The trip count is wave-uniform.
   const int64_t G = (int64_t)gridDim.x * 16;
   for (int64_t base = (int64_t)blockIdx.x * 16 + ((threadIdx.x >> 6) << 2); base < n_items; base += G) {
   const int64_t gid = base + ((threadIdx.x >> 4) & 3);
-  FItem it{0, 0, 0, 0, 0}, ot{0, 0, 0, 0, 0};
+  FItem it{0, 0, 0, 0, 0};
   if (gid < n_items) it = items[gid];
-  if constexpr (!FIB) {
-    const int64_t og = base + (l >> 2);  // item of this lane's tile rows
-    if (og < n_items) ot = items[og];
-  }
   float Nc[E][J];
   float v[E];
 #pragma unroll
@@ -537,17 +482,39 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
     // steps are neutralised below (w = 0, no decay)
     const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
     const float xv = it.len > 0 ? val[p] : 0.f;
-    // phase 1: g of the 16 elements (matrix-core tiles, or the fiber table)
-    float g16[16][E];
-    if constexpr (FIB)
-      fiber_tile_g<J>(it, t0, l, fid, gfib, g16);
-    else
-      tile_g<N, J, R, T>(ot, t0, lw, idx, nnz, cp, bop, g16);
+    // phase 1: w of the 16 elements (or, with fibers, their precomputed g)
+    float w[16][FIB ? E : RE];
+    if constexpr (FIB) {
+      const int fv = it.len > 0 ? fid[p] : 0;
+      static_for<0, 16>([&](auto S) {
+        constexpr int s = decltype(S)::value;
+        const int64_t fb = (int64_t)bcast16i<s>(fv) * J;
+        const bool sv = (t0 + s) < it.len;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          // unconditional load (fv is a valid fiber, the column clamped) so
+          // that all 16 loads are in flight together; masked afterwards
+          const int j = l + 16 * e;
+          const float gv = gfib[fb + min(j, J - 1)];
+          w[s][e] = (sv && j < J) ? gv : 0.f;
+        }
+      });
+    } else {
+      int ix[N - 1];
+#pragma unroll
+      for (int k = 0; k < N - 1; ++k)
+        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (int)(R * sizeof(T)) : 0;
+      gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
+    }
     static_for<0, 16>([&](auto S) {
       constexpr int s = decltype(S)::value;
       float g[E];
+      if constexpr (FIB) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) g[e] = g16[s][e];
+        for (int e = 0; e < E; ++e) g[e] = w[s][e];
+      } else {
+        shared_g<J, R>(Bw, w[s], g);
+      }
       constexpr int JK = J >= 16 ? 16 : J;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -780,6 +747,39 @@ __device__ __forceinline__ floatx4 gather_row_product(const CPtrs<N, T>& cp, con
   return vld ? w : zero;
 }
 
+// Indices and values of one trip: kUnroll groups of P elements of a segment
+// from position t0.  Positions past the end are clamped to the segment's last
+// element (a valid address), so that the loads need no branch, and flagged.
+template <int N>
+struct Trip {
+  bool vl[kUnroll];
+  uint32_t o[kUnroll];
+  int32_t ik[kUnroll][N > 1 ? N - 1 : 1];
+  float xv[kUnroll];
+};
+
+template <int N, int P, bool PERM>
+__device__ __forceinline__ void load_trip(Trip<N>& L, const Seg& S, int t0, int slot, const int32_t* __restrict__ idx,
+                                          int64_t nnz, const float* __restrict__ xs,
+                                          const int32_t* __restrict__ perm) {
+  const int last = max(S.len - 1, 0);
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const int t = t0 + u * P + slot;
+    L.vl[u] = t < S.len;
+    L.o[u] = (uint32_t)min(t, last);
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) L.ik[u][k] = (idx + (int64_t)k * nnz + S.start)[L.o[u]];
+    L.xv[u] = PERM ? xs[(perm + S.start)[L.o[u]]] : (xs + S.start)[L.o[u]];
+  }
+}
+
+// A wavefront walks its segments gw, gw + nw, ... trip by trip.  While the
+// gathers of one trip are in flight it already loads the indices of the next
+// trip (the first trip of its next segment at a segment's end, whose
+// descriptor was read one segment ahead), so that every trip costs one memory
+// round trip instead of two.  A segment of length 0 stands in past the last.
+
 // MODE 0: s = sum e w (core gradient); MODE 1: t = sum -e w (gradient of 1/2 sum e^2);
 // MODE 2: t = sum delta w with delta from the caller (input order, via perm).
 template <int N, int J, int R, int MODE, class T>
@@ -792,77 +792,96 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
   constexpr int QL = R / 4;
   constexpr int P = 64 / QL;
   constexpr int GJ = (J + P - 1) / P;
+  constexpr int U = kUnroll;
   __shared__ float red[4][J * R];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int slot = lane / QL, q = lane % QL;
   const int64_t nw = (int64_t)gridDim.x * 4;
+  const float* xs = MODE == 2 ? up : val;
   float Gp[GJ][4];
 #pragma unroll
   for (int u = 0; u < GJ; ++u)
 #pragma unroll
     for (int c = 0; c < 4; ++c) Gp[u][c] = 0.f;
-  for (int64_t sg = (int64_t)blockIdx.x * 4 + wave; sg < nseg; sg += nw) {
-    const Seg S = segs[sg];
+  // C(m) slice and A(m) entries of a segment's row
+  auto row_loads = [&](const Seg& X, floatx4& cr, float (&ar)[GJ]) {
+    if (MODE != 2) cr = load4(Cm + (int64_t)X.row * R + 4 * q);
+#pragma unroll
+    for (int u = 0; u < GJ; ++u) {
+      const int j = slot + P * u;
+      ar[u] = j < J ? to_f(Am[(int64_t)X.row * J + j]) : 0.f;
+    }
+  };
+  int64_t sg = (int64_t)blockIdx.x * 4 + wave;
+  if (sg < nseg) {
+    const Seg none{0, 0, 0};
+    Seg S = segs[sg];
+    Seg Sq = sg + nw < nseg ? segs[sg + nw] : none;
     floatx4 crow = {0.f, 0.f, 0.f, 0.f};
-    if (MODE != 2) crow = load4(Cm + (int64_t)S.row * R + 4 * q);
+    float arow[GJ];
+    row_loads(S, crow, arow);
+    Trip<N> cur;
+    load_trip<N, P, MODE == 2>(cur, S, 0, slot, idx, nnz, xs, perm);
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    // U element groups per trip: all index loads, then all gathers, then the
-    // arithmetic, so that each wavefront keeps U times more loads in flight.
-    for (int t0 = 0; t0 < S.len; t0 += P * kUnroll) {
-      bool vl[kUnroll];
-      int64_t pp[kUnroll];
-      int32_t ik[kUnroll][N - 1];
-      float xv[kUnroll];
+    int t0 = 0;
+    for (;;) {
+      floatx4 w[U];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        // positions past the end are clamped to the last element (a valid
-        // address) so that the loads need no branch; their terms are zeroed
-        vl[u] = (t0 + u * P + slot) < S.len;
-        const uint32_t o = (uint32_t)min(t0 + u * P + slot, S.len - 1);
-        pp[u] = S.start + o;
+      for (int u = 0; u < U; ++u) w[u] = gather_row_product<N, R, T>(cp, cur.ik[u], cur.vl[u], q);
+      const bool seg_end = t0 + P * U >= S.len;
+      const Seg& Sn = seg_end ? Sq : S;
+      Trip<N> nxt;
+      load_trip<N, P, MODE == 2>(nxt, Sn, seg_end ? 0 : t0 + P * U, slot, idx, nnz, xs, perm);
+      floatx4 crow_n = crow;
+      float arow_n[GJ];
 #pragma unroll
-        for (int k = 0; k < N - 1; ++k) ik[u][k] = (idx + (int64_t)k * nnz + S.start)[o];
-        if (MODE == 2)
-          xv[u] = up[(perm + S.start)[o]];
-        else
-          xv[u] = (val + S.start)[o];
-      }
-      floatx4 w[kUnroll];
+      for (int u = 0; u < GJ; ++u) arow_n[u] = arow[u];
+      if (seg_end) row_loads(Sq, crow_n, arow_n);
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) w[u] = gather_row_product<N, R, T>(cp, ik[u], vl[u], q);
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < U; ++u) {
         float d;
         if (MODE == 2) {
-          d = vl[u] ? xv[u] : 0.f;
+          d = cur.vl[u] ? cur.xv[u] : 0.f;
         } else {
           float xh = crow[0] * w[u][0];
           xh = fmaf(crow[1], w[u][1], xh);
           xh = fmaf(crow[2], w[u][2], xh);
           xh = fmaf(crow[3], w[u][3], xh);
           xh = group_sum<QL>(xh);
-          d = vl[u] ? (MODE == 0 ? xv[u] - xh : xh - xv[u]) : 0.f;
+          d = cur.vl[u] ? (MODE == 0 ? cur.xv[u] - xh : xh - cur.xv[u]) : 0.f;
         }
         acc[0] = fmaf(d, w[u][0], acc[0]);
         acc[1] = fmaf(d, w[u][1], acc[1]);
         acc[2] = fmaf(d, w[u][2], acc[2]);
         acc[3] = fmaf(d, w[u][3], acc[3]);
       }
-    }
+      if (seg_end) {
 #pragma unroll
-    for (int off = QL; off < 64; off <<= 1)
+        for (int off = QL; off < 64; off <<= 1)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] += __shfl_xor(acc[c], off);
-    if (tseg && slot == 0) *reinterpret_cast<floatx4*>(tseg + sg * R + 4 * q) = acc;
+          for (int c = 0; c < 4; ++c) acc[c] += __shfl_xor(acc[c], off);
+        if (tseg && slot == 0) *reinterpret_cast<floatx4*>(tseg + sg * R + 4 * q) = acc;
 #pragma unroll
-    for (int u = 0; u < GJ; ++u) {
-      const int j = slot + P * u;
-      if (j < J) {
-        const float aj = to_f(Am[(int64_t)S.row * J + j]);
+        for (int u = 0; u < GJ; ++u) {
+          const int j = slot + P * u;
+          if (j < J)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Gp[u][c] = fmaf(aj, acc[c], Gp[u][c]);
+            for (int c = 0; c < 4; ++c) Gp[u][c] = fmaf(arow[u], acc[c], Gp[u][c]);
+        }
+        sg += nw;
+        if (sg >= nseg) break;
+        S = Sq;
+        Sq = sg + nw < nseg ? segs[sg + nw] : none;
+        crow = crow_n;
+#pragma unroll
+        for (int u = 0; u < GJ; ++u) arow[u] = arow_n[u];
+        acc = floatx4{0.f, 0.f, 0.f, 0.f};
+        t0 = 0;
+      } else {
+        t0 += P * U;
       }
+      cur = nxt;
     }
   }
 #pragma unroll
@@ -937,45 +956,55 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
                                               const int32_t* __restrict__ perm, float* __restrict__ out) {
   constexpr int QL = R / 4;
   constexpr int P = 64 / QL;
+  constexpr int U = kUnroll;
   __shared__ double red[4];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int slot = lane / QL, q = lane % QL;
   const int64_t nw = (int64_t)gridDim.x * 4;
   double sse = 0.0;
-  for (int64_t sg = (int64_t)blockIdx.x * 4 + wave; sg < nseg; sg += nw) {
-    const Seg S = segs[sg];
-    const floatx4 crow = load4(Cm + (int64_t)S.row * R + 4 * q);
-    for (int t0 = 0; t0 < S.len; t0 += P * kUnroll) {
-      bool vl[kUnroll];
-      int64_t pp[kUnroll];
-      int32_t ik[kUnroll][N - 1];
-      float xv[kUnroll];
+  int64_t sg = (int64_t)blockIdx.x * 4 + wave;
+  if (sg < nseg) {
+    const Seg none{0, 0, 0};
+    Seg S = segs[sg];
+    Seg Sq = sg + nw < nseg ? segs[sg + nw] : none;
+    floatx4 crow = load4(Cm + (int64_t)S.row * R + 4 * q);
+    Trip<N> cur;
+    load_trip<N, P, false>(cur, S, 0, slot, idx, nnz, val, nullptr);
+    int t0 = 0;
+    for (;;) {
+      floatx4 w[U];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        vl[u] = (t0 + u * P + slot) < S.len;
-        const uint32_t o = (uint32_t)min(t0 + u * P + slot, S.len - 1);
-        pp[u] = S.start + o;
+      for (int u = 0; u < U; ++u) w[u] = gather_row_product<N, R, T>(cp, cur.ik[u], cur.vl[u], q);
+      const bool seg_end = t0 + P * U >= S.len;
+      const Seg& Sn = seg_end ? Sq : S;
+      Trip<N> nxt;
+      load_trip<N, P, false>(nxt, Sn, seg_end ? 0 : t0 + P * U, slot, idx, nnz, val, nullptr);
+      const floatx4 crow_n = seg_end ? load4(Cm + (int64_t)Sq.row * R + 4 * q) : crow;
 #pragma unroll
-        for (int k = 0; k < N - 1; ++k) ik[u][k] = (idx + (int64_t)k * nnz + S.start)[o];
-        xv[u] = (val + S.start)[o];
-      }
-      floatx4 w[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) w[u] = gather_row_product<N, R, T>(cp, ik[u], vl[u], q);
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < U; ++u) {
         float xh = crow[0] * w[u][0];
         xh = fmaf(crow[1], w[u][1], xh);
         xh = fmaf(crow[2], w[u][2], xh);
         xh = fmaf(crow[3], w[u][3], xh);
         xh = group_sum<QL>(xh);
-        if (vl[u] && q == 0) {
-          const float e = xv[u] - xh;
+        if (cur.vl[u] && q == 0) {
+          const float e = cur.xv[u] - xh;
           sse += (double)e * (double)e;
-          if (out) out[perm[pp[u]]] = xh;
+          if (out) out[perm[S.start + cur.o[u]]] = xh;
         }
       }
+      if (seg_end) {
+        sg += nw;
+        if (sg >= nseg) break;
+        S = Sq;
+        Sq = sg + nw < nseg ? segs[sg + nw] : none;
+        t0 = 0;
+      } else {
+        t0 += P * U;
+      }
+      crow = crow_n;
+      cur = nxt;
     }
   }
 #pragma unroll
@@ -1121,8 +1150,8 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr,
   const float flr = (float)lr, c1 = (float)(-lr * lam), gp = (float)(lr / rho);
   if (FIB) {
     KTimer tm(P, FT_K_FIBER_G, s);
-    // kFiberTiles tiles of 16 fibers per wavefront, four wavefronts per workgroup
-    const int64_t per_block = 4 * 16 * kFiberTiles;
+    // kFiberBatches batches of 16 fibers per 16-lane group, 16 groups per workgroup
+    const int64_t per_block = 16 * 16 * kFiberBatches;
     hipLaunchKernelGGL((k_fiber_g<N, J, R, T>), dim3((unsigned)((M.n_fibers + per_block - 1) / per_block)), dim3(256),
                        0, s, D.fib_idx, M.n_fibers, cp, Bm, P->gfib);
   }

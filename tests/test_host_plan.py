@@ -107,7 +107,7 @@ def test_calls_before_upload_fail_cleanly():
 
 
 def test_fiber_counts():
-    """Mode-m fibers (Section 3.2): distinct tuples of the other indices; shared when they hold >= 4/3 elements."""
+    """Mode-m fibers (Section 3.2): distinct tuples of the other indices; shared when they hold >= 4 elements."""
     dims = [40, 30, 20]
     c, _ = synth.coords(dims, 6000, 1.2, seed=8)
     v = np.ones(c.shape[1], dtype=np.float32)
@@ -118,6 +118,6 @@ def test_fiber_counts():
         nf = len(np.unique(key))
         info = plan.mode_info(m)
         assert info["fibers"] == nf
-        assert info["fiber_shared"] == int(nf * 4 <= c.shape[1] * 3)
+        assert info["fiber_shared"] == int(nf * 4 <= c.shape[1])
     off = ft.Plan(dims, 8, 8, c, v, keep_host=True, upload=False, fiber_share=False)
     assert all(off.mode_info(m)["fiber_shared"] == 0 for m in range(3))
