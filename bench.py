@@ -30,7 +30,7 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic(w, nnz, row_counts, chunk, fibers):
+def algorithmic(w, nnz, row_counts, head, fibers):
     """Per-epoch algorithmic flops and bytes per kernel family (formulas in the design notes).
 
     fibers[m] is the number of mode-m fibers when g = B(m) w is shared per fiber
@@ -47,8 +47,8 @@ def algorithmic(w, nnz, row_counts, chunk, fibers):
     a_bytes = [d * J * 4 for d in w.dims]
     for m in range(N):
         L = row_counts[m]
-        heavy = L > chunk
-        comp = float(np.sum(np.where(heavy, L - chunk, 0)))
+        heavy = L > head
+        comp = float(np.sum(np.where(heavy, L - head, 0)))
         app = float(nnz - comp)
         others = sum(c_bytes) - c_bytes[m]
         if fibers[m] is None:
@@ -152,7 +152,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=3_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
-    ap.add_argument("--chunk", type=int, default=0, help="rows longer than this are split (0: library default)")
+    ap.add_argument("--chunk", type=int, default=0, help="elements per chunk map of a long row (0: library default)")
+    ap.add_argument("--head", type=int, default=0,
+                    help="rows longer than this are split into a head and chunks (0: library default)")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16"],
                     help="parameter storage: FP32, or BF16 copies with FP32 masters and accumulation")
     ap.add_argument("--no-fiber-share", action="store_true",
@@ -191,7 +193,7 @@ def main():
     c, v, A, B = synth.make(w, nnz=nnz)
     log(f"generated in {time.time() - t:.1f} s")
     t = time.time()
-    plan = ft.Plan(w.dims, J, R, c, v, chunk=args.chunk, fiber_share=not args.no_fiber_share)
+    plan = ft.Plan(w.dims, J, R, c, v, chunk=args.chunk, head=args.head, fiber_share=not args.no_fiber_share)
     log(f"plan built and uploaded in {time.time() - t:.1f} s ({plan.device_bytes() / 2**30:.2f} GiB on device)")
     prm = ft.Params(A, B, storage=args.storage)
     ft.refresh(plan, prm)
@@ -225,7 +227,7 @@ def main():
     counts = [np.bincount(c[m], minlength=w.dims[m]) for m in range(N)]
     infos = [plan.mode_info(m) for m in range(N)]
     fibers = [info["fibers"] if info["fiber_shared"] else None for info in infos]
-    alg = algorithmic(w, nnz, counts, args.chunk or 512, fibers)
+    alg = algorithmic(w, nnz, counts, args.head or args.chunk or 512, fibers)
     kernels = {}
     for k, (ms, n) in prof.items():
         if n == 0:
@@ -237,7 +239,8 @@ def main():
         t_s = kernels[dom]["ms_per_step"] / 1e3
         flops, byts = alg.get(dom, [0.0, 0.0])
         traffic = (counter_traffic(args.workload, dom)
-                   if args.nnz is None and not args.chunk and args.storage == "f32" and not args.no_fiber_share
+                   if args.nnz is None and not args.chunk and not args.head and args.storage == "f32"
+                   and not args.no_fiber_share
                    else None)
         launches = kernels[dom]["launches_per_step"]
         if dom in ("factor_compose", "factor_apply"):

@@ -63,7 +63,10 @@ typedef struct {
   int32_t J[FT_MAX_ORDER];      /* factor rank per mode; must all be equal */
   int32_t R;                    /* core rank */
   int64_t nnz;                  /* |Omega|, 0..2^32-1 */
-  int32_t chunk;                /* rows with more elements are split into chunks of this many (0: 512) */
+  int32_t chunk;                /* elements per chunk map of a long row (0: 512) */
+  int32_t head;                 /* rows of at most this many elements are updated as one serial chain; a
+                                   longer row has its first `head` elements updated in place and the rest
+                                   cut into chunks (0: chunk) */
   int32_t fanin;                /* chunk maps folded per combine step (0 or above the maximum: 16 for
                                    J <= 16, 8 above); a row with at most fanin maps has them applied in
                                    sequence to its first chunk's result */
@@ -99,9 +102,9 @@ typedef struct {
   int64_t rows;          /* I_m */
   int64_t nonempty_rows; /* rows with at least one element */
   int64_t max_row;       /* largest row length */
-  int64_t light_rows;    /* rows of at most `chunk` elements, updated in one piece */
-  int64_t heavy_rows;    /* longer rows, split into chunks */
-  int64_t chunks;        /* chunks of heavy rows, first chunks included */
+  int64_t light_rows;    /* rows of at most `head` elements, updated in one piece */
+  int64_t heavy_rows;    /* longer rows: a head plus chunks */
+  int64_t chunks;        /* pieces of heavy rows, heads included */
   int64_t segments;      /* pieces of rows used by the core, loss and gradient passes */
   int32_t combine_levels;
   int32_t fiber_shared;  /* 1 if the factor pass shares g per fiber in this mode */

@@ -58,6 +58,7 @@ class FtDesc(ctypes.Structure):
         ("R", ctypes.c_int32),
         ("nnz", ctypes.c_int64),
         ("chunk", ctypes.c_int32),
+        ("head", ctypes.c_int32),
         ("fanin", ctypes.c_int32),
         ("flags", ctypes.c_int32),
     ]

@@ -30,7 +30,7 @@ class Plan:
     coords: int32 [order][nnz] (host), vals: float32 [nnz] (host)."""
 
     def __init__(self, dims, J, R, coords, vals, chunk=0, fanin=0, keep_host=False, with_perm=False, upload=True,
-                 fiber_share=True):
+                 fiber_share=True, head=0):
         lib = load()
         coords = np.ascontiguousarray(coords, dtype=np.int32)
         vals = np.ascontiguousarray(vals, dtype=np.float32)
@@ -46,6 +46,7 @@ class Plan:
         d.R = int(R)
         d.nnz = int(coords.shape[1])
         d.chunk = int(chunk)
+        d.head = int(head)
         d.fanin = int(fanin)
         d.flags = ((_lib.FT_KEEP_HOST if keep_host else 0) | (_lib.FT_WITH_PERM if with_perm else 0)
                    | (0 if fiber_share else _lib.FT_NO_FIBER_SHARE))

@@ -101,7 +101,7 @@ struct ft_plan {
   ft_desc desc{};
   int N = 0, J = 0, R = 0;
   int64_t nnz = 0;
-  int chunk = 512, fanin = 16;
+  int chunk = 512, head = 512, fanin = 16;
   std::vector<ft::ModeMeta> meta;
   std::vector<ft::ModeHost> host;
   std::vector<ft::ModeDev> dev;

@@ -166,8 +166,10 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
     return fail(FT_ERR_NOMEM, "host allocation failed while sorting mode " + std::to_string(m));
   }
 
-  // factor work lists
-  const int64_t chunk = P->chunk;
+  // factor work lists: a row of at most `head` elements is one serial item;
+  // a longer row is a head item (its first `head` elements, updated in
+  // place) followed by chunk items whose maps the combine applies in order
+  const int64_t chunk = P->chunk, hl = P->head;
   std::vector<FItem> light, head;
   int64_t n_heavy = 0, n_maps = 0, max_row = 0, nonempty = 0;
   std::vector<int64_t> heavy_rows, heavy_base, heavy_nmaps;
@@ -176,21 +178,21 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
     if (L == 0) continue;
     ++nonempty;
     max_row = std::max(max_row, L);
-    if (L <= chunk) {
+    if (L <= hl) {
       light.push_back(FItem{s, (int32_t)L, (int32_t)i, 0, ITEM_LIGHT});
       continue;
     }
-    int64_t K = (L + chunk - 1) / chunk;
-    head.push_back(FItem{s, (int32_t)chunk, (int32_t)i, (int32_t)n_heavy, ITEM_HEAD});
+    const int64_t K = (L - hl + chunk - 1) / chunk;  // chunk maps after the head
+    head.push_back(FItem{s, (int32_t)hl, (int32_t)i, (int32_t)n_heavy, ITEM_HEAD});
     heavy_rows.push_back(i);
     heavy_base.push_back(n_maps);
-    heavy_nmaps.push_back(K - 1);
-    for (int64_t c = 1; c < K; ++c) {
-      int64_t st = s + c * chunk;
-      H.compose.push_back(
-          FItem{st, (int32_t)std::min(chunk, L - c * chunk), (int32_t)i, (int32_t)(n_maps + c - 1), ITEM_COMPOSE});
+    heavy_nmaps.push_back(K);
+    for (int64_t c = 0; c < K; ++c) {
+      const int64_t st = s + hl + c * chunk;
+      H.compose.push_back(FItem{st, (int32_t)std::min(chunk, L - hl - c * chunk), (int32_t)i, (int32_t)(n_maps + c),
+                                ITEM_COMPOSE});
     }
-    n_maps += K - 1;
+    n_maps += K;
     ++n_heavy;
   }
   if (n_maps > 0x7FFFFFFF || n_heavy > 0x7FFFFFFF) return fail(FT_ERR_SHAPE, "too many chunks");
@@ -309,7 +311,8 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
   if (!supported(d->order, d->J[0], d->R))
     return fail(FT_ERR_UNSUPPORTED, "no kernels compiled for order " + std::to_string(d->order) + ", J " +
                                         std::to_string(d->J[0]) + ", R " + std::to_string(d->R));
-  if (d->chunk < 0 || d->fanin < 0 || d->fanin == 1) return fail(FT_ERR_ARG, "bad chunk or fanin");
+  if (d->chunk < 0 || d->head < 0 || d->fanin < 0 || d->fanin == 1)
+    return fail(FT_ERR_ARG, "bad chunk, head or fanin");
   if ((d->flags & FT_WITH_PERM) && d->nnz > 0x7FFFFFFF) return fail(FT_ERR_SHAPE, "FT_WITH_PERM needs nnz < 2^31");
   const int N = d->order;
   const int64_t nnz = d->nnz;
@@ -343,6 +346,7 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
   P->R = d->R;
   P->nnz = nnz;
   P->chunk = d->chunk ? d->chunk : 512;
+  P->head = d->head ? d->head : P->chunk;
   P->fanin = std::min(d->fanin ? d->fanin : max_fanin(d->J[0]), max_fanin(d->J[0]));
   try {
     P->meta.resize(N);

@@ -29,10 +29,11 @@ def netflix():
     return w, c, v, A, B, plan, prm
 
 
-def _sample_rows(counts, chunk=512):
+def _sample_rows(counts, chunk=512, head=512):
+    """The longest rows and rows near the piece boundaries of the default plan (head, then chunks)."""
     order = np.argsort(-counts, kind="stable")
     picks = [order[0], order[min(5, len(order) - 1)]]
-    for target in (chunk * 3 + 7, chunk + 1, chunk, chunk // 2, 3):
+    for target in (head + chunk * 3 + 7, head + 1, head, head // 2, chunk + 1, 3):
         near = np.argsort(np.abs(counts - target), kind="stable")
         picks.append(near[0])
     return np.unique(np.array(picks))

@@ -16,12 +16,13 @@ from tests.gpu_common import bf16_scale, delta_ok, to_np
 pytestmark = pytest.mark.gpu
 
 
-def _sample_rows(counts, chunk=512, max_len=None):
+def _sample_rows(counts, chunk=512, head=512, max_len=None):
+    """The longest rows and rows near the piece boundaries of the default plan (head, then chunks)."""
     order = np.argsort(-counts, kind="stable")
     if max_len is not None:
         order = order[counts[order] <= max_len]
     picks = [order[0], order[min(7, len(order) - 1)]]
-    for target in (chunk * 2 + 3, chunk + 1, chunk // 2, 2):
+    for target in (head + chunk * 2 + 3, head + 1, head // 2, chunk + 1, 2):
         picks.append(np.argsort(np.abs(counts - target), kind="stable")[0])
     return np.unique(np.array(picks))
 

@@ -42,7 +42,8 @@ def test_csr_order_and_permutation(order):
     c = np.concatenate([c, c[:, :17]], axis=1)
     v = np.concatenate([v, v[:17] + 1])
     nnz = c.shape[1]
-    plan = _plan(dims, J, R, c, v, chunk=16)
+    chunk, head = 16, 40
+    plan = _plan(dims, J, R, c, v, chunk=chunk, head=head)
     for m in range(order):
         row_ptr, idx, vals, perm = plan.host_csr(m)
         assert row_ptr[0] == 0 and row_ptr[-1] == nnz
@@ -57,9 +58,10 @@ def test_csr_order_and_permutation(order):
         assert key_tuples == sorted(key_tuples)
         info = plan.mode_info(m)
         counts = np.diff(row_ptr)
-        assert info["light_rows"] == int(np.sum((counts > 0) & (counts <= 16)))
-        assert info["heavy_rows"] == int(np.sum(counts > 16))
-        assert info["chunks"] == int(np.sum(np.where(counts > 16, (counts + 15) // 16, 0)))
+        assert info["light_rows"] == int(np.sum((counts > 0) & (counts <= head)))
+        assert info["heavy_rows"] == int(np.sum(counts > head))
+        # a head plus ceil((L - head) / chunk) chunks per heavy row
+        assert info["chunks"] == int(np.sum(np.where(counts > head, 1 + (counts - head + chunk - 1) // chunk, 0)))
         assert info["max_row"] == int(counts.max())
 
 
