@@ -278,15 +278,19 @@ __device__ __forceinline__ void shared_g(const float (&Bw)[J >= 16 ? J / 16 : 1]
 // fiber f (w_f = prod_{n != m} C(n)[i_n, :] is the same for every element of
 // the fiber).  Same lane layout and operation order as the per-element path,
 // so the factor pass gives the same bits either way.  Each 16-lane group takes
-// kFiberBatches batches of 16 fibers and issues all their gathers first.
-constexpr int kFiberBatches = 2;
+// fiber_batches batches of 16 fibers and issues all their gathers first (one
+// batch when the gathered values of two would not fit in registers).
+template <int N, int R>
+constexpr int fiber_batches() {
+  return (N - 1) * (R >= 16 ? R / 16 : 1) > 8 ? 1 : 2;
+}
 
 template <int N, int J, int R, class T>
 __global__ __launch_bounds__(256) void k_fiber_g(const int32_t* __restrict__ fib_idx, int64_t nfib, CPtrs<N, T> cp,
                                                  const T* __restrict__ Bm, float* __restrict__ gfib) {
   constexpr int E = J >= 16 ? J / 16 : 1;
   constexpr int RE = R >= 16 ? R / 16 : 1;
-  constexpr int FB = kFiberBatches;
+  constexpr int FB = fiber_batches<N, R>();
   const int l = threadIdx.x & 15;
   const int64_t f00 = ((int64_t)blockIdx.x * 16 + (threadIdx.x >> 4)) * 16 * FB;
   float Bw[E][R];
@@ -728,7 +732,12 @@ __global__ __launch_bounds__(256) void k_combine_final(const CItem* __restrict__
 // Segment passes (core gradient, loss, forward, gradient).  A wavefront takes
 // segments gw, gw + nw, ... (a fixed assignment), R/4 lanes per element.
 
-constexpr int kUnroll = 4;
+// groups of P elements per trip: fewer at high order, where each element
+// holds N - 1 indices in registers
+template <int N>
+constexpr int trip_unroll() {
+  return N > 4 ? 2 : 4;
+}
 
 // prod over the gathered 16-byte slices of C rows.  Invalid slots carry index
 // 0 (a valid row) and are zeroed after the loads, so that the loads need no
@@ -747,15 +756,17 @@ __device__ __forceinline__ floatx4 gather_row_product(const CPtrs<N, T>& cp, con
   return vld ? w : zero;
 }
 
-// Indices and values of one trip: kUnroll groups of P elements of a segment
-// from position t0.  Positions past the end are clamped to the segment's last
-// element (a valid address), so that the loads need no branch, and flagged.
+// Indices and values of one trip: trip_unroll groups of P elements of a
+// segment from position t0.  Positions past the end are clamped to the
+// segment's last element (a valid address), so that the loads need no
+// branch, and flagged.
 template <int N>
 struct Trip {
-  bool vl[kUnroll];
-  uint32_t o[kUnroll];
-  int32_t ik[kUnroll][N > 1 ? N - 1 : 1];
-  float xv[kUnroll];
+  static constexpr int U = trip_unroll<N>();
+  bool vl[U];
+  uint32_t o[U];
+  int32_t ik[U][N > 1 ? N - 1 : 1];
+  float xv[U];
 };
 
 template <int N, int P, bool PERM>
@@ -764,7 +775,7 @@ __device__ __forceinline__ void load_trip(Trip<N>& L, const Seg& S, int t0, int 
                                           const int32_t* __restrict__ perm) {
   const int last = max(S.len - 1, 0);
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) {
+  for (int u = 0; u < Trip<N>::U; ++u) {
     const int t = t0 + u * P + slot;
     L.vl[u] = t < S.len;
     L.o[u] = (uint32_t)min(t, last);
@@ -792,7 +803,7 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
   constexpr int QL = R / 4;
   constexpr int P = 64 / QL;
   constexpr int GJ = (J + P - 1) / P;
-  constexpr int U = kUnroll;
+  constexpr int U = trip_unroll<N>();
   __shared__ float red[4][J * R];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -956,7 +967,7 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
                                               const int32_t* __restrict__ perm, float* __restrict__ out) {
   constexpr int QL = R / 4;
   constexpr int P = 64 / QL;
-  constexpr int U = kUnroll;
+  constexpr int U = trip_unroll<N>();
   __shared__ double red[4];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1084,7 +1095,9 @@ __global__ __launch_bounds__(256) void k_predict(const int32_t* __restrict__ coo
 // ---------------------------------------------------------------------------
 // dispatch
 
-#define FT_CONFIGS(X) X(3, 8, 8) X(3, 16, 16) X(3, 32, 32) X(4, 8, 8) X(4, 32, 32) X(8, 8, 16)
+#define FT_CONFIGS(X)                                                                                       \
+  X(3, 8, 8) X(3, 16, 16) X(3, 32, 32) X(4, 8, 8) X(4, 32, 32) X(8, 8, 16) X(5, 32, 32) X(6, 32, 32) X(7, 32, 32) \
+      X(8, 32, 32) X(9, 32, 32) X(10, 32, 32)
 
 constexpr int key(int N, int J, int R) { return (N * 64 + J) * 64 + R; }
 
@@ -1150,8 +1163,8 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr,
   const float flr = (float)lr, c1 = (float)(-lr * lam), gp = (float)(lr / rho);
   if (FIB) {
     KTimer tm(P, FT_K_FIBER_G, s);
-    // kFiberBatches batches of 16 fibers per 16-lane group, 16 groups per workgroup
-    const int64_t per_block = 16 * 16 * kFiberBatches;
+    // fiber_batches batches of 16 fibers per 16-lane group, 16 groups per workgroup
+    const int64_t per_block = 16 * 16 * fiber_batches<N, R>();
     hipLaunchKernelGGL((k_fiber_g<N, J, R, T>), dim3((unsigned)((M.n_fibers + per_block - 1) / per_block)), dim3(256),
                        0, s, D.fib_idx, M.n_fibers, cp, Bm, P->gfib);
   }

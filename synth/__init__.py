@@ -148,6 +148,15 @@ WORKLOADS = {
     "order8": Workload("order8", [10_000] * 8, 50_000_000, 1.05, "normal3", [8] * 8, 16),
     "order4": Workload("order4", [1_000_000, 100_000, 10_000, 1_000], 200_000_000, 1.1, "int1to5", [32] * 4, 32),
 }
+# The paper's synthetic sweeps (Section 5.1 table of synthetic tensors; Sections 5.4, 5.5): uniform random
+# coordinates, values 1..5, J = R = 32.  Order 3..10 with every dimension 10,000 and 100M elements; order 3
+# with every dimension 1,000 and 20M..100M elements (density 2 %..10 %).
+for _n in range(3, 11):
+    WORKLOADS[f"sweep_order{_n}"] = Workload(f"sweep_order{_n}", [10_000] * _n, 100_000_000, 0.0, "int1to5",
+                                             [32] * _n, 32)
+for _m in (20, 40, 60, 80, 100):
+    WORKLOADS[f"sweep_density{_m}"] = Workload(f"sweep_density{_m}", [1_000] * 3, _m * 1_000_000, 0.0, "int1to5",
+                                               [32] * 3, 32)
 
 
 def make(w: Workload, nnz: int | None = None, dims=None):

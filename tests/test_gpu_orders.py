@@ -1,0 +1,52 @@
+"""GPU against the FP64 oracle at orders 5..10 with J = R = 32 (the configurations of the order sweep).
+
+One Algorithm-2 iteration (factor and core pass of every mode with C refreshes) and the loss, on small
+seeded tensors shaped so that every code path of these instantiations runs: Zipf rows longer than the
+chunk (chunk maps, several combine levels) and, in a second tensor, mode-0 fibers that hold many elements
+(shared g).  A, B are drawn with sigma 0.35 so that products of N - 1 C rows stay far from zero and the
+updates test more than the decay term.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import delta_ok, gpu_setup, make_problem, oracle_model, to_np
+
+pytestmark = pytest.mark.gpu
+
+ORDERS = [5, 6, 7, 8, 9, 10]
+
+
+def _shapes(order):
+    zipf_rows = ([20] * order, 20_000, 1.1, {"chunk": 32})
+    space = 200 * 2 ** (order - 1)
+    fibers = ([200] + [2] * (order - 1), space // 2, 0.0, {})
+    return {"zipf_rows": zipf_rows, "fibers": fibers}
+
+
+@pytest.mark.parametrize("shape", ["zipf_rows", "fibers"])
+@pytest.mark.parametrize("order", ORDERS)
+def test_iteration_high_order(order, shape):
+    import paper_2210_06014_amd as ft
+
+    J = R = 32
+    dims, nnz, zipf, kw = _shapes(order)[shape]
+    c, v, A, B = make_problem(dims, nnz, zipf, J, R, seed=40 + order, sigma=0.35)
+    plan, prm = gpu_setup(dims, J, R, c, v, A, B, **kw)
+    infos = [plan.mode_info(m) for m in range(order)]
+    if shape == "zipf_rows":
+        assert infos[0]["heavy_rows"] > 0 and max(i["combine_levels"] for i in infos) >= 2
+    else:
+        assert infos[0]["fiber_shared"] == 1
+    orc = oracle_model(dims, J, R, c, v, A, B)
+    A0 = [a.astype(np.float64) for a in A]
+    B0 = [b.astype(np.float64) for b in B]
+    ft.epoch(plan, prm, 1e-3, 1e-2, 1e-3, 1e-2)
+    orc.epoch(1e-3, 1e-2, 1e-3, 1e-2)
+    for n in range(order):
+        ok, err, bound = delta_ok(to_np(prm.A[n]), orc.A[n], A0[n])
+        assert ok, (order, shape, "A", n, err, bound)
+        ok, err, bound = delta_ok(to_np(prm.B[n]), orc.B[n], B0[n])
+        assert ok, (order, shape, "B", n, err, bound)
+    got = to_np(ft.loss(plan, prm, 1e-2, 1e-2))
+    ref = np.asarray(orc.loss(1e-2, 1e-2))
+    np.testing.assert_allclose(got, ref, rtol=1e-4)
