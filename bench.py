@@ -262,6 +262,19 @@ def main():
                 kernels[k]["alg_tflops"] = alg[k][0] / t_k / 1e12
                 kernels[k]["alg_gbs"] = alg[k][1] / t_k / 1e9
 
+    # the per-pass measures of the paper's Table 5: N |Omega| / time of the factor passes (with their C
+    # refreshes and shared-g passes) and of the core passes (with their reductions and refreshes)
+    passes = None
+    if kernels:
+        refresh = kernels.get("refresh", {}).get("ms_per_step", 0.0)
+        t_f = sum(kernels[k]["ms_per_step"] for k in ("factor_compose", "factor_apply", "combine", "fiber_g")
+                  if k in kernels) + refresh / 2
+        t_c = sum(kernels[k]["ms_per_step"] for k in ("segsum", "reduce") if k in kernels) + refresh / 2
+        passes = {"factor_ms": t_f, "core_ms": t_c, "factor_nnz_per_s": N * nnz / (t_f / 1e3),
+                  "core_nnz_per_s": N * nnz / (t_c / 1e3), "factor_core_nnz_updates_per_s": 2 * N * nnz / ((t_f + t_c) / 1e3),
+                  "note": "kernel time only (library events); the refresh time is split evenly between the passes; "
+                  "the reduce timer, counted with the core pass, also holds the loss pass's FP64 reductions"}
+
     cpu = None
     if not args.no_cpu_baseline:
         s = min(args.cpu_sample, nnz)
@@ -293,6 +306,7 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "passes": passes,
         "kernels": kernels,
     }
     print(json.dumps(line), flush=True)
