@@ -159,6 +159,8 @@ def main():
                     help="parameter storage: FP32, or BF16 copies with FP32 masters and accumulation")
     ap.add_argument("--no-fiber-share", action="store_true",
                     help="form g = B(m) w per element instead of once per mode-m fiber (Section 3.2 ablation)")
+    ap.add_argument("--no-c-cache", action="store_true",
+                    help="factor and core passes form C rows from A and B on use (FastTucker's cost; Table 5 ablation)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -193,7 +195,8 @@ def main():
     c, v, A, B = synth.make(w, nnz=nnz)
     log(f"generated in {time.time() - t:.1f} s")
     t = time.time()
-    plan = ft.Plan(w.dims, J, R, c, v, chunk=args.chunk, head=args.head, fiber_share=not args.no_fiber_share)
+    plan = ft.Plan(w.dims, J, R, c, v, chunk=args.chunk, head=args.head, fiber_share=not args.no_fiber_share,
+                   c_cache=not args.no_c_cache)
     log(f"plan built and uploaded in {time.time() - t:.1f} s ({plan.device_bytes() / 2**30:.2f} GiB on device)")
     prm = ft.Params(A, B, storage=args.storage)
     ft.refresh(plan, prm)
@@ -240,7 +243,7 @@ def main():
         flops, byts = alg.get(dom, [0.0, 0.0])
         traffic = (counter_traffic(args.workload, dom)
                    if args.nnz is None and not args.chunk and not args.head and args.storage == "f32"
-                   and not args.no_fiber_share
+                   and not args.no_fiber_share and not args.no_c_cache
                    else None)
         launches = kernels[dom]["launches_per_step"]
         if dom in ("factor_compose", "factor_apply"):

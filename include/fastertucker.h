@@ -55,6 +55,11 @@ typedef enum {
 #define FT_KEEP_HOST 1 /* keep the host copy of the plan after upload (ft_plan_host_csr) */
 #define FT_WITH_PERM 2 /* keep element permutations on the device (ft_forward, ft_grad with upstream) */
 #define FT_NO_FIBER_SHARE 4 /* compute g for every element instead of once per fiber (Section 3.2); same results */
+#define FT_NO_C_CACHE 8     /* factor and core passes form every C(n) row they need from A(n) and B(n) on use
+                               instead of reading the cached C (the cost structure of FastTucker, kept for the
+                               comparison of Table 5; implies FT_NO_FIBER_SHARE).  Order 3, J = R = 16 and FP32
+                               storage only (FT_ERR_UNSUPPORTED otherwise); loss, predict and gradient calls
+                               still read C, which the refreshes keep current */
 
 /* Shape of the problem and of the plan. */
 typedef struct {
@@ -70,7 +75,7 @@ typedef struct {
   int32_t fanin;                /* chunk maps folded per combine step (0 or above the maximum: 16 for
                                    J <= 16, 8 above); a row with at most fanin maps has them applied in
                                    sequence to its first chunk's result */
-  int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM | FT_NO_FIBER_SHARE */
+  int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM | FT_NO_FIBER_SHARE | FT_NO_C_CACHE */
 } ft_desc;
 
 /* ft_params.storage */

@@ -21,6 +21,7 @@ ft_status check_params(const ft_plan* P, const ft_params* p) {
   if (!p) return fail(FT_ERR_ARG, "null params");
   if (p->storage != FT_STORE_F32 && p->storage != FT_STORE_BF16) return fail(FT_ERR_ARG, "unknown storage");
   const bool b16 = p->storage == FT_STORE_BF16;
+  if (b16 && P->no_c_cache) return fail(FT_ERR_UNSUPPORTED, "FT_NO_C_CACHE is built for FP32 storage only");
   for (int n = 0; n < P->N; ++n) {
     if (!p->A[n] || !p->B[n] || (!b16 && !p->C[n]) || (b16 && (!p->A16[n] || !p->B16[n] || !p->C16[n])))
       return fail(FT_ERR_ARG, "null parameter pointer for mode " + std::to_string(n));

@@ -259,6 +259,48 @@ __device__ __forceinline__ void gather_w(const CPtrs<N, T>& cp, const int (&ixb)
   });
 }
 
+// The same w without the C cache (FastTucker's cost, kept for the Table 5
+// comparison): each C(n) row is formed on use as A(n)[i, :] B(n).  Lane j
+// loads A(n)[i, j]; a row broadcast against the lane's column of B(n) then
+// gives C(n)[i, r] in lane r (J = R = 16).
+template <int N>
+struct NoC {
+  const float* A[N > 1 ? N - 1 : 1];  // A(n) of the other modes, in table order
+  const float* B[N > 1 ? N - 1 : 1];
+};
+
+template <int N>
+__device__ __forceinline__ void load_nc_cols(const NoC<N>& nc, int l, float (&Bc)[N > 1 ? N - 1 : 1][16]) {
+#pragma unroll
+  for (int k = 0; k < N - 1; ++k)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) Bc[k][j] = nc.B[k][j * 16 + l];
+}
+
+// ix[k]: row index of element (lane t)'s k-th other mode
+template <int N>
+__device__ __forceinline__ void gather_w_nc(const NoC<N>& nc, const float (&Bc)[N > 1 ? N - 1 : 1][16],
+                                            const int (&ix)[N > 1 ? N - 1 : 1], int l, int t0, int len,
+                                            float (&w)[16][1]) {
+  float av[16][N - 1];
+  static_for<0, 16>([&](auto S) {
+    constexpr int s = decltype(S)::value;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) av[s][k] = nc.A[k][(int64_t)bcast16i<s>(ix[k]) * 16 + l];
+  });
+  static_for<0, 16>([&](auto S) {
+    constexpr int s = decltype(S)::value;
+    float prod = 0.f;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+      float c = 0.f;
+      dot_bcast16(c, av[s][k], Bc[k]);
+      prod = k == 0 ? c : prod * c;
+    }
+    w[s][0] = (t0 + s) < len ? prod : 0.f;
+  });
+}
+
 // g = B(m) w for this lane's elements j = l + 16 e; w_r comes from lane r % 16.
 template <int J, int R>
 __device__ __forceinline__ void shared_g(const float (&Bw)[J >= 16 ? J / 16 : 1][R], const float (&ws)[R >= 16 ? R / 16 : 1],
@@ -332,13 +374,14 @@ __global__ __launch_bounds__(256) void k_fiber_g(const int32_t* __restrict__ fib
   }
 }
 
-template <int N, int J, int R, class T, bool FIB>
+template <int N, int J, int R, class T, bool FIB, bool NC = false>
 __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ items, int64_t n_items,
                                                       const int32_t* __restrict__ idx, int64_t nnz,
                                                       const float* __restrict__ val, CPtrs<N, T> cp,
                                                       const T* __restrict__ Bm, float* __restrict__ Am,
                                                       float* __restrict__ hvec, float lr, float c1,
-                                                      const int32_t* __restrict__ fid, const float* __restrict__ gfib) {
+                                                      const int32_t* __restrict__ fid, const float* __restrict__ gfib,
+                                                      NoC<N> nc) {
   constexpr int E = J >= 16 ? J / 16 : 1;
   constexpr int RE = R >= 16 ? R / 16 : 1;
   const int l = threadIdx.x & 15;
@@ -349,6 +392,9 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
 #pragma unroll
     for (int r = 0; r < R; ++r) Bw[e][r] = (!FIB && j < J) ? to_f(Bm[j * R + r]) : 0.f;
   }
+  static_assert(!NC || (J == 16 && R == 16 && !FIB), "the no-C-cache variant is built for J = R = 16");
+  float Bc[N > 1 ? N - 1 : 1][16];
+  if constexpr (NC) load_nc_cols<N>(nc, l, Bc);
   // Persistent groups: the four groups of a wavefront take four consecutive
   // items (similar lengths, the lists are sorted) and then stride by the grid,
   // so B(m) is loaded once per group.  The trip count is wave-uniform.
@@ -396,8 +442,11 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
       int ix[N - 1];
 #pragma unroll
       for (int k = 0; k < N - 1; ++k)
-        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (int)(R * sizeof(T)) : 0;
-      gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
+        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (NC ? 1 : (int)(R * sizeof(T))) : 0;
+      if constexpr (NC)
+        gather_w_nc<N>(nc, Bc, ix, l, t0, it.len, w);
+      else
+        gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
     }
     static_for<0, 16>([&](auto S) {
       constexpr int s = decltype(S)::value;
@@ -443,14 +492,14 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
 //     Nm <- Nm - gp g (g + Nm^T g)^T     (Nm = prod (I - gp g g^T) - I)
 //     v  <- v + (-lr lam) v + lr (x - v.g) g
 // (v is the state reached from a = 0).  Lane j keeps column j of Nm.
-template <int N, int J, int R, class T, bool FIB>
+template <int N, int J, int R, class T, bool FIB, bool NC = false>
 __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict__ items, int64_t n_items,
                                                         const int32_t* __restrict__ idx, int64_t nnz,
                                                         const float* __restrict__ val, CPtrs<N, T> cp,
                                                         const T* __restrict__ Bm, float* __restrict__ maps,
                                                         double* __restrict__ map_scale, float lr, float c1, float gp,
                                                         double rho, const int32_t* __restrict__ fid,
-                                                        const float* __restrict__ gfib) {
+                                                        const float* __restrict__ gfib, NoC<N> nc) {
   constexpr int E = J >= 16 ? J / 16 : 1;
   constexpr int RE = R >= 16 ? R / 16 : 1;
   constexpr int MS = J * J + J;
@@ -462,6 +511,9 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
 #pragma unroll
     for (int r = 0; r < R; ++r) Bw[e][r] = (!FIB && j < J) ? to_f(Bm[j * R + r]) : 0.f;
   }
+  static_assert(!NC || (J == 16 && R == 16 && !FIB), "the no-C-cache variant is built for J = R = 16");
+  float Bc[N > 1 ? N - 1 : 1][16];
+  if constexpr (NC) load_nc_cols<N>(nc, l, Bc);
   // Persistent groups: the four groups of a wavefront take four consecutive
   // items (similar lengths, the lists are sorted) and then stride by the grid,
   // so B(m) is loaded once per group.  The trip count is wave-uniform.
@@ -507,8 +559,11 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
       int ix[N - 1];
 #pragma unroll
       for (int k = 0; k < N - 1; ++k)
-        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (int)(R * sizeof(T)) : 0;
-      gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
+        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (NC ? 1 : (int)(R * sizeof(T))) : 0;
+      if constexpr (NC)
+        gather_w_nc<N>(nc, Bc, ix, l, t0, it.len, w);
+      else
+        gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
     }
     static_for<0, 16>([&](auto S) {
       constexpr int s = decltype(S)::value;
@@ -907,6 +962,63 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
     partials[(int64_t)blockIdx.x * J * R + e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
 
+// Core gradient without the C cache (the Table 5 comparison; N = 3,
+// J = R = 16): one segment per 16-lane group.  Lane r forms C(n)[i, r] of the
+// other modes from their A rows, C(m)[row, r] once per segment, then
+// s_r = sum_x e_x w_r and G[:, r] += a_row s_r.  The sixteen groups' partials
+// of a workgroup are summed in a fixed order.
+template <int N>
+__global__ __launch_bounds__(256) void k_core_nc(const Seg* __restrict__ segs, int64_t nseg,
+                                                 const int32_t* __restrict__ idx, int64_t nnz,
+                                                 const float* __restrict__ val, NoC<N> nc,
+                                                 const float* __restrict__ Am, const float* __restrict__ Bm,
+                                                 float* __restrict__ partials) {
+  constexpr int J = 16, R = 16;
+  __shared__ float red[16][J * R];
+  const int l = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  float Bc[N - 1][16];
+  load_nc_cols<N>(nc, l, Bc);
+  float Bmc[16], Gc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    Bmc[j] = Bm[j * R + l];
+    Gc[j] = 0.f;
+  }
+  const int64_t ng = (int64_t)gridDim.x * 16;
+  for (int64_t sg = (int64_t)blockIdx.x * 16 + grp; sg < nseg; sg += ng) {
+    const Seg S = segs[sg];
+    const float arow = Am[(int64_t)S.row * J + l];
+    float crow = 0.f;
+    dot_bcast16(crow, arow, Bmc);  // C(m)[row, l]
+    float sacc = 0.f;
+    for (int t0 = 0; t0 < S.len; t0 += 16) {
+      const int64_t p = S.start + min(t0 + l, S.len - 1);
+      const float xv = val[p];
+      int ix[N - 1];
+#pragma unroll
+      for (int k = 0; k < N - 1; ++k) ix[k] = idx[(int64_t)k * nnz + p];
+      float w[16][1];
+      gather_w_nc<N>(nc, Bc, ix, l, t0, S.len, w);
+      static_for<0, 16>([&](auto SS) {
+        constexpr int s = decltype(SS)::value;
+        const float xh = group_sum<16>(crow * w[s][0]);
+        const float e = bcast16<s>(xv) - xh;
+        sacc = fmaf(e, w[s][0], sacc);  // w = 0 past the end of the segment
+      });
+    }
+    axpy_bcast16(Gc, arow, sacc);  // G[j][l] += a_j s_l
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) red[grp][j * R + l] = Gc[j];
+  __syncthreads();
+  for (int e = threadIdx.x; e < J * R; e += 256) {
+    float acc = 0.f;
+#pragma unroll
+    for (int g = 0; g < 16; ++g) acc += red[g][e];
+    partials[(int64_t)blockIdx.x * J * R + e] = acc;
+  }
+}
+
 // Sum of the workgroup partials in a fixed order, in two stages: first every
 // block of kFold consecutive partials (many workgroups), then the blocks.
 constexpr int kFold = 32;
@@ -1153,11 +1265,17 @@ unsigned factor_blocks(const void* kernel, int64_t n_items) {
   return (unsigned)std::max<int64_t>(1, (n_items + 15) / 16);
 }
 
-template <int N, int J, int R, class T, bool FIB>
+template <int N, int J, int R, class T, bool FIB, bool NC = false>
 hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
   const ModeMeta& M = P->meta[m];
   const ModeDev& D = P->dev[m];
   const CPtrs<N, T> cp = others<N, T>(p, m);
+  NoC<N> nc{};
+  if (NC)
+    for (int k = 0; k < N - 1; ++k) {
+      nc.A[k] = p->A[(m + 1 + k) % N];
+      nc.B[k] = p->B[(m + 1 + k) % N];
+    }
   const T* Bm = Store<T>::B(p, m);
   const double rho = 1.0 - lr * lam;
   const float flr = (float)lr, c1 = (float)(-lr * lam), gp = (float)(lr / rho);
@@ -1170,16 +1288,17 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr,
   }
   if (M.n_compose > 0) {
     KTimer tm(P, FT_K_FACTOR_COMPOSE, s);
-    hipLaunchKernelGGL((k_factor_compose<N, J, R, T, FIB>),
-                       dim3(factor_blocks((const void*)k_factor_compose<N, J, R, T, FIB>, M.n_compose)), dim3(256), 0,
-                       s, D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm, P->maps, P->map_scale, flr, c1, gp,
-                       rho, D.fid, P->gfib);
+    hipLaunchKernelGGL((k_factor_compose<N, J, R, T, FIB, NC>),
+                       dim3(factor_blocks((const void*)k_factor_compose<N, J, R, T, FIB, NC>, M.n_compose)), dim3(256),
+                       0, s, D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm, P->maps, P->map_scale, flr, c1, gp,
+                       rho, D.fid, P->gfib, nc);
   }
   if (M.n_apply > 0) {
     KTimer tm(P, FT_K_FACTOR_APPLY, s);
-    hipLaunchKernelGGL((k_factor_apply<N, J, R, T, FIB>),
-                       dim3(factor_blocks((const void*)k_factor_apply<N, J, R, T, FIB>, M.n_apply)), dim3(256), 0, s,
-                       D.apply, M.n_apply, D.idx, P->nnz, D.val, cp, Bm, p->A[m], P->hvec, flr, c1, D.fid, P->gfib);
+    hipLaunchKernelGGL((k_factor_apply<N, J, R, T, FIB, NC>),
+                       dim3(factor_blocks((const void*)k_factor_apply<N, J, R, T, FIB, NC>, M.n_apply)), dim3(256), 0,
+                       s, D.apply, M.n_apply, D.idx, P->nnz, D.val, cp, Bm, p->A[m], P->hvec, flr, c1, D.fid, P->gfib,
+                       nc);
   }
   for (size_t L = 0; L < M.level_len.size(); ++L) {
     KTimer tm(P, FT_K_COMBINE, s);
@@ -1196,6 +1315,12 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr,
 
 template <int N, int J, int R, class T>
 hipError_t factor_impl(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
+  if (P->no_c_cache) {
+    if constexpr (N == 3 && J == 16 && R == 16 && std::is_same<T, float>::value)
+      return factor_launch<N, J, R, T, false, true>(P, m, p, lr, lam, s);
+    else
+      return hipErrorInvalidValue;  // rejected at plan creation and in the parameter checks
+  }
   return P->meta[m].use_fiber ? factor_launch<N, J, R, T, true>(P, m, p, lr, lam, s)
                               : factor_launch<N, J, R, T, false>(P, m, p, lr, lam, s);
 }
@@ -1367,9 +1492,28 @@ static hipError_t segsum(const ft_plan* P, int m, const ft_params* p, int mode, 
 #undef X
 }
 
+// core gradient partials without the C cache (N = 3, J = R = 16, FP32 only)
+static hipError_t core_nc(const ft_plan* P, int m, const ft_params* p, hipStream_t s, int* nb) {
+  if (P->N != 3 || P->J != 16 || P->R != 16 || bf16(p)) return hipErrorInvalidValue;
+  const ModeMeta& M = P->meta[m];
+  const ModeDev& D = P->dev[m];
+  NoC<3> nc{};
+  for (int k = 0; k < 2; ++k) {
+    nc.A[k] = p->A[(m + 1 + k) % 3];
+    nc.B[k] = p->B[(m + 1 + k) % 3];
+  }
+  int64_t b = (M.n_segs + 15) / 16;
+  b = std::max<int64_t>(1, std::min<int64_t>(b, std::min(kPartials, resident_blocks((const void*)k_core_nc<3>))));
+  *nb = (int)b;
+  KTimer tm(P, FT_K_SEGSUM, s);
+  hipLaunchKernelGGL(k_core_nc<3>, dim3((unsigned)b), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, nc,
+                     p->A[m], p->B[m], P->partials);
+  return hipGetLastError();
+}
+
 hipError_t launch_core_grad(const ft_plan* P, int m, const ft_params* p, hipStream_t s) {
   int nb = 0;
-  hipError_t e = segsum(P, m, p, 0, nullptr, nullptr, s, &nb);
+  hipError_t e = P->no_c_cache ? core_nc(P, m, p, s, &nb) : segsum(P, m, p, 0, nullptr, nullptr, s, &nb);
   if (e != hipSuccess) return e;
   return reduce_partials(P, nb, nullptr, P->gbuf, 0.f, 0.f, 0.f, 0, s);
 }
@@ -1377,7 +1521,7 @@ hipError_t launch_core_grad(const ft_plan* P, int m, const ft_params* p, hipStre
 hipError_t launch_core_update(const ft_plan* P, int m, const ft_params* p, double lr, double lam, float* G_out,
                               hipStream_t s) {
   int nb = 0;
-  hipError_t e = segsum(P, m, p, 0, nullptr, nullptr, s, &nb);
+  hipError_t e = P->no_c_cache ? core_nc(P, m, p, s, &nb) : segsum(P, m, p, 0, nullptr, nullptr, s, &nb);
   if (e != hipSuccess) return e;
   const float inv = P->nnz > 0 ? (float)(1.0 / (double)P->nnz) : 0.f;
   return reduce_partials(P, nb, p->B[m], G_out, (float)lr, (float)lam, inv, P->nnz > 0 ? 1 : 0, s);

@@ -259,7 +259,7 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   // share g per fiber when fibers hold 4 elements or more on average: per
   // element, reading g saves about a quarter of the cost of forming it per
   // fiber (measured on MI355X with the Netflix-shaped workload)
-  M.use_fiber = !(P->desc.flags & FT_NO_FIBER_SHARE) && M.n_fibers > 0 && M.n_fibers * 4 <= nnz &&
+  M.use_fiber = !(P->desc.flags & (FT_NO_FIBER_SHARE | FT_NO_C_CACHE)) && M.n_fibers > 0 && M.n_fibers * 4 <= nnz &&
                 M.n_fibers <= 0x7FFFFFFF;
   if (!M.use_fiber) {
     H.fid.clear();
@@ -313,6 +313,8 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
                                         std::to_string(d->J[0]) + ", R " + std::to_string(d->R));
   if (d->chunk < 0 || d->head < 0 || d->fanin < 0 || d->fanin == 1)
     return fail(FT_ERR_ARG, "bad chunk, head or fanin");
+  if ((d->flags & FT_NO_C_CACHE) && !(d->order == 3 && d->J[0] == 16 && d->R == 16))
+    return fail(FT_ERR_UNSUPPORTED, "FT_NO_C_CACHE is built for order 3 with J = R = 16 only");
   if ((d->flags & FT_WITH_PERM) && d->nnz > 0x7FFFFFFF) return fail(FT_ERR_SHAPE, "FT_WITH_PERM needs nnz < 2^31");
   const int N = d->order;
   const int64_t nnz = d->nnz;
@@ -347,6 +349,7 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
   P->nnz = nnz;
   P->chunk = d->chunk ? d->chunk : 512;
   P->head = d->head ? d->head : P->chunk;
+  P->no_c_cache = (d->flags & FT_NO_C_CACHE) != 0;
   P->fanin = std::min(d->fanin ? d->fanin : max_fanin(d->J[0]), max_fanin(d->J[0]));
   try {
     P->meta.resize(N);

@@ -234,3 +234,30 @@ def test_fiber_shared_g_is_bitwise_equal(case):
         assert torch.equal(a, b)
     for a, b in zip(outs[1], outs[3]):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("case", ["zipf3_j16", "zipf3_j16_smallchunk"])
+def test_no_c_cache_variant(case):
+    """FT_NO_C_CACHE (the FastTucker cost, Table 5): every C row formed from A and B on use; same results."""
+    import paper_2210_06014_amd as ft
+
+    name, dims, nnz, zipf, J, R, kw = [c for c in CASES if c[0] == case][0]
+    c, v, A, B = make_problem(dims, nnz, zipf, J, R, seed=11)
+    plan, prm = gpu_setup(dims, J, R, c, v, A, B, c_cache=False, **kw)
+    orc = oracle_model(dims, J, R, c, v, A, B)
+    for m in range(3):
+        before = orc.A[m].copy()
+        ft.factor_pass(plan, prm, m, 1e-3, 1e-2)
+        orc.factor_pass(m, 1e-3, 1e-2)
+        ok, err, bound = delta_ok(to_np(prm.A[m]), orc.A[m], before)
+        assert ok, (name, "factor", m, err, bound)
+        ft.refresh(plan, prm, m)
+        orc.refresh(m)
+    for m in range(3):
+        before = orc.B[m].copy()
+        ft.core_pass(plan, prm, m, 1e-3, 1e-2)
+        orc.core_pass(m, 1e-3, 1e-2)
+        ok, err, bound = delta_ok(to_np(prm.B[m]), orc.B[m], before)
+        assert ok, (name, "core", m, err, bound)
+        ft.refresh(plan, prm, m)
+        orc.refresh(m)

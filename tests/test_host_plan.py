@@ -123,3 +123,17 @@ def test_fiber_counts():
         assert info["fiber_shared"] == int(nf * 4 <= c.shape[1])
     off = ft.Plan(dims, 8, 8, c, v, keep_host=True, upload=False, fiber_share=False)
     assert all(off.mode_info(m)["fiber_shared"] == 0 for m in range(3))
+
+
+def test_no_c_cache_flag():
+    """FT_NO_C_CACHE: built for order 3 with J = R = 16; it turns fiber sharing off."""
+    dims = [40, 30, 20]
+    c, _ = synth.coords(dims, 6000, 1.2, seed=8)
+    v = np.ones(c.shape[1], dtype=np.float32)
+    plan = ft.Plan(dims, 16, 16, c, v, keep_host=True, upload=False, c_cache=False)
+    assert all(plan.mode_info(m)["fiber_shared"] == 0 for m in range(3))
+    for J, R, d in ((8, 8, dims), (32, 32, dims), (16, 16, dims + [5])):
+        cc, _ = synth.coords(d, 500, 0.0, seed=3)
+        with pytest.raises(ft.FtError) as e:
+            ft.Plan(d, J, R, cc, np.ones(500, dtype=np.float32), keep_host=True, upload=False, c_cache=False)
+        assert e.value.status == 4
