@@ -812,32 +812,43 @@ __device__ __forceinline__ floatx4 gather_row_product(const CPtrs<N, T>& cp, con
 }
 
 // Indices and values of one trip: trip_unroll groups of P elements of a
-// segment from position t0.  Positions past the end are clamped to the
-// segment's last element (a valid address), so that the loads need no
-// branch, and flagged.
-template <int N>
+// segment from position t0.  Each element is loaded once, by lane
+// (element - t0) % 64, and handed to the R/4 lanes that gather for it by a
+// cross-lane permute (the LDS crossbar), so that an index load carries 64
+// distinct addresses: the address units, which bound these passes, see a
+// quarter of the index loads.  Positions past the end are clamped to the
+// segment's last element (a valid address), so the loads need no branch.
+template <int N, int P>
 struct Trip {
   static constexpr int U = trip_unroll<N>();
-  bool vl[U];
-  uint32_t o[U];
-  int32_t ik[U][N > 1 ? N - 1 : 1];
-  float xv[U];
+  static constexpr int NL = (U * P + 63) / 64;  // element loads per lane
+  int32_t ik[NL][N > 1 ? N - 1 : 1];
+  float xv[NL];
 };
 
 template <int N, int P, bool PERM>
-__device__ __forceinline__ void load_trip(Trip<N>& L, const Seg& S, int t0, int slot, const int32_t* __restrict__ idx,
-                                          int64_t nnz, const float* __restrict__ xs,
+__device__ __forceinline__ void load_trip(Trip<N, P>& L, const Seg& S, int t0, int lane,
+                                          const int32_t* __restrict__ idx, int64_t nnz, const float* __restrict__ xs,
                                           const int32_t* __restrict__ perm) {
   const int last = max(S.len - 1, 0);
 #pragma unroll
-  for (int u = 0; u < Trip<N>::U; ++u) {
-    const int t = t0 + u * P + slot;
-    L.vl[u] = t < S.len;
-    L.o[u] = (uint32_t)min(t, last);
+  for (int h = 0; h < Trip<N, P>::NL; ++h) {
+    const uint32_t o = (uint32_t)min(t0 + 64 * h + lane, last);
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) L.ik[u][k] = (idx + (int64_t)k * nnz + S.start)[L.o[u]];
-    L.xv[u] = PERM ? xs[(perm + S.start)[L.o[u]]] : (xs + S.start)[L.o[u]];
+    for (int k = 0; k < N - 1; ++k) L.ik[h][k] = (idx + (int64_t)k * nnz + S.start)[o];
+    L.xv[h] = PERM ? xs[(perm + S.start)[o]] : (xs + S.start)[o];
   }
+}
+
+// indices and value of element u P + slot of a trip, from the lane that loaded it
+template <int N, int P, int u>
+__device__ __forceinline__ void trip_elem(const Trip<N, P>& L, int slot, int32_t (&ik)[N > 1 ? N - 1 : 1],
+                                          float& xv) {
+  constexpr int h = (u * P) / 64;
+  const int src = (u * P + slot) & 63;
+#pragma unroll
+  for (int k = 0; k < N - 1; ++k) ik[k] = __shfl(L.ik[h][k], src);
+  xv = __shfl(L.xv[h], src);
 }
 
 // A wavefront walks its segments gw, gw + nw, ... trip by trip.  While the
@@ -887,18 +898,26 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
     floatx4 crow = {0.f, 0.f, 0.f, 0.f};
     float arow[GJ];
     row_loads(S, crow, arow);
-    Trip<N> cur;
-    load_trip<N, P, MODE == 2>(cur, S, 0, slot, idx, nnz, xs, perm);
+    Trip<N, P> cur;
+    load_trip<N, P, MODE == 2>(cur, S, 0, lane, idx, nnz, xs, perm);
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     int t0 = 0;
     for (;;) {
+      int32_t ik[U][N > 1 ? N - 1 : 1];
+      float xv[U];
+      bool vl[U];
+      static_for<0, U>([&](auto UU) {
+        constexpr int u = decltype(UU)::value;
+        trip_elem<N, P, u>(cur, slot, ik[u], xv[u]);
+        vl[u] = t0 + u * P + slot < S.len;
+      });
       floatx4 w[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) w[u] = gather_row_product<N, R, T>(cp, cur.ik[u], cur.vl[u], q);
+      for (int u = 0; u < U; ++u) w[u] = gather_row_product<N, R, T>(cp, ik[u], vl[u], q);
       const bool seg_end = t0 + P * U >= S.len;
       const Seg& Sn = seg_end ? Sq : S;
-      Trip<N> nxt;
-      load_trip<N, P, MODE == 2>(nxt, Sn, seg_end ? 0 : t0 + P * U, slot, idx, nnz, xs, perm);
+      Trip<N, P> nxt;
+      load_trip<N, P, MODE == 2>(nxt, Sn, seg_end ? 0 : t0 + P * U, lane, idx, nnz, xs, perm);
       floatx4 crow_n = crow;
       float arow_n[GJ];
 #pragma unroll
@@ -908,14 +927,14 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
       for (int u = 0; u < U; ++u) {
         float d;
         if (MODE == 2) {
-          d = cur.vl[u] ? cur.xv[u] : 0.f;
+          d = vl[u] ? xv[u] : 0.f;
         } else {
           float xh = crow[0] * w[u][0];
           xh = fmaf(crow[1], w[u][1], xh);
           xh = fmaf(crow[2], w[u][2], xh);
           xh = fmaf(crow[3], w[u][3], xh);
           xh = group_sum<QL>(xh);
-          d = cur.vl[u] ? (MODE == 0 ? cur.xv[u] - xh : xh - cur.xv[u]) : 0.f;
+          d = vl[u] ? (MODE == 0 ? xv[u] - xh : xh - xv[u]) : 0.f;
         }
         acc[0] = fmaf(d, w[u][0], acc[0]);
         acc[1] = fmaf(d, w[u][1], acc[1]);
@@ -1092,17 +1111,25 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
     Seg S = segs[sg];
     Seg Sq = sg + nw < nseg ? segs[sg + nw] : none;
     floatx4 crow = load4(Cm + (int64_t)S.row * R + 4 * q);
-    Trip<N> cur;
-    load_trip<N, P, false>(cur, S, 0, slot, idx, nnz, val, nullptr);
+    Trip<N, P> cur;
+    load_trip<N, P, false>(cur, S, 0, lane, idx, nnz, val, nullptr);
     int t0 = 0;
     for (;;) {
+      int32_t ik[U][N > 1 ? N - 1 : 1];
+      float xv[U];
+      bool vl[U];
+      static_for<0, U>([&](auto UU) {
+        constexpr int u = decltype(UU)::value;
+        trip_elem<N, P, u>(cur, slot, ik[u], xv[u]);
+        vl[u] = t0 + u * P + slot < S.len;
+      });
       floatx4 w[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) w[u] = gather_row_product<N, R, T>(cp, cur.ik[u], cur.vl[u], q);
+      for (int u = 0; u < U; ++u) w[u] = gather_row_product<N, R, T>(cp, ik[u], vl[u], q);
       const bool seg_end = t0 + P * U >= S.len;
       const Seg& Sn = seg_end ? Sq : S;
-      Trip<N> nxt;
-      load_trip<N, P, false>(nxt, Sn, seg_end ? 0 : t0 + P * U, slot, idx, nnz, val, nullptr);
+      Trip<N, P> nxt;
+      load_trip<N, P, false>(nxt, Sn, seg_end ? 0 : t0 + P * U, lane, idx, nnz, val, nullptr);
       const floatx4 crow_n = seg_end ? load4(Cm + (int64_t)Sq.row * R + 4 * q) : crow;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -1111,10 +1138,10 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
         xh = fmaf(crow[2], w[u][2], xh);
         xh = fmaf(crow[3], w[u][3], xh);
         xh = group_sum<QL>(xh);
-        if (cur.vl[u] && q == 0) {
-          const float e = cur.xv[u] - xh;
+        if (vl[u] && q == 0) {
+          const float e = xv[u] - xh;
           sse += (double)e * (double)e;
-          if (out) out[perm[S.start + cur.o[u]]] = xh;
+          if (out) out[perm[S.start + (t0 + u * P + slot)]] = xh;
         }
       }
       if (seg_end) {
