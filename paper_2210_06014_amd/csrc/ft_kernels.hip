@@ -794,21 +794,50 @@ constexpr int trip_unroll() {
   return N > 4 ? 2 : 4;
 }
 
-// prod over the gathered 16-byte slices of C rows.  Invalid slots carry index
-// 0 (a valid row) and are zeroed after the loads, so that the loads need no
-// branch and all of them can be in flight together.
-template <int N, int R, class T>
-__device__ __forceinline__ floatx4 gather_row_product(const CPtrs<N, T>& cp, const int32_t (&ik)[N > 1 ? N - 1 : 1],
-                                                      bool vld, int q) {
-  const uint32_t qb = (uint32_t)(4 * q * sizeof(T));
-  floatx4 w = load4(reinterpret_cast<const T*>(reinterpret_cast<const char*>(cp.p[0]) +
-                                               ((uint32_t)ik[0] * (uint32_t)(R * sizeof(T)) + qb)));
+// Values per lane in the segment passes: one 16-byte load of a C row, 4 FP32
+// or 8 BF16 values, so a row takes R/4 (FP32) or R/8 (BF16) lanes.
+template <class T>
+constexpr int vpl() {
+  return 16 / (int)sizeof(T);
+}
+
+__device__ __forceinline__ void load16(const float* p, float (&o)[4]) {
+  const floatx4 u = *reinterpret_cast<const floatx4*>(p);
 #pragma unroll
-  for (int k = 1; k < N - 1; ++k)
-    w *= load4(reinterpret_cast<const T*>(reinterpret_cast<const char*>(cp.p[k]) +
-                                          ((uint32_t)ik[k] * (uint32_t)(R * sizeof(T)) + qb)));
-  const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
-  return vld ? w : zero;
+  for (int c = 0; c < 4; ++c) o[c] = u[c];
+}
+__device__ __forceinline__ void load16(const uint16_t* p, float (&o)[8]) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    o[2 * c] = __uint_as_float(w[c] << 16);
+    o[2 * c + 1] = __uint_as_float(w[c] & 0xFFFF0000u);
+  }
+}
+
+// prod over the gathered 16-byte slices (lane q of the element) of its C
+// rows, in table order; zero for an invalid slot.  Invalid slots carry index
+// 0 (a valid row), so the loads need no branch and are all in flight together.
+template <int N, int R, class T>
+__device__ __forceinline__ void gather_slices(const CPtrs<N, T>& cp, const int32_t (&ik)[N > 1 ? N - 1 : 1], bool vld,
+                                              int q, float (&w)[vpl<T>()]) {
+  constexpr int V = vpl<T>();
+  const uint32_t qb = (uint32_t)(16 * q);
+  load16(reinterpret_cast<const T*>(reinterpret_cast<const char*>(cp.p[0]) +
+                                    ((uint32_t)ik[0] * (uint32_t)(R * sizeof(T)) + qb)),
+         w);
+#pragma unroll
+  for (int k = 1; k < N - 1; ++k) {
+    float t[V];
+    load16(reinterpret_cast<const T*>(reinterpret_cast<const char*>(cp.p[k]) +
+                                      ((uint32_t)ik[k] * (uint32_t)(R * sizeof(T)) + qb)),
+           t);
+#pragma unroll
+    for (int c = 0; c < V; ++c) w[c] *= t[c];
+  }
+#pragma unroll
+  for (int c = 0; c < V; ++c) w[c] = vld ? w[c] : 0.f;
 }
 
 // Indices and values of one trip: trip_unroll groups of P elements of a
@@ -866,7 +895,8 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
                                                 const T* __restrict__ Cm, const T* __restrict__ Am,
                                                 const float* __restrict__ up, const int32_t* __restrict__ perm,
                                                 float* __restrict__ partials, float* __restrict__ tseg) {
-  constexpr int QL = R / 4;
+  constexpr int V = vpl<T>();
+  constexpr int QL = R / V;
   constexpr int P = 64 / QL;
   constexpr int GJ = (J + P - 1) / P;
   constexpr int U = trip_unroll<N>();
@@ -876,14 +906,14 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
   const int slot = lane / QL, q = lane % QL;
   const int64_t nw = (int64_t)gridDim.x * 4;
   const float* xs = MODE == 2 ? up : val;
-  float Gp[GJ][4];
+  float Gp[GJ][V];
 #pragma unroll
   for (int u = 0; u < GJ; ++u)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) Gp[u][c] = 0.f;
+    for (int c = 0; c < V; ++c) Gp[u][c] = 0.f;
   // C(m) slice and A(m) entries of a segment's row
-  auto row_loads = [&](const Seg& X, floatx4& cr, float (&ar)[GJ]) {
-    if (MODE != 2) cr = load4(Cm + (int64_t)X.row * R + 4 * q);
+  auto row_loads = [&](const Seg& X, float (&cr)[V], float (&ar)[GJ]) {
+    if (MODE != 2) load16(Cm + (int64_t)X.row * R + V * q, cr);
 #pragma unroll
     for (int u = 0; u < GJ; ++u) {
       const int j = slot + P * u;
@@ -895,12 +925,16 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
     const Seg none{0, 0, 0};
     Seg S = segs[sg];
     Seg Sq = sg + nw < nseg ? segs[sg + nw] : none;
-    floatx4 crow = {0.f, 0.f, 0.f, 0.f};
+    float crow[V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) crow[c] = 0.f;
     float arow[GJ];
     row_loads(S, crow, arow);
     Trip<N, P> cur;
     load_trip<N, P, MODE == 2>(cur, S, 0, lane, idx, nnz, xs, perm);
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    float acc[V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) acc[c] = 0.f;
     int t0 = 0;
     for (;;) {
       int32_t ik[U][N > 1 ? N - 1 : 1];
@@ -911,15 +945,16 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
         trip_elem<N, P, u>(cur, slot, ik[u], xv[u]);
         vl[u] = t0 + u * P + slot < S.len;
       });
-      floatx4 w[U];
+      float w[U][V];
 #pragma unroll
-      for (int u = 0; u < U; ++u) w[u] = gather_row_product<N, R, T>(cp, ik[u], vl[u], q);
+      for (int u = 0; u < U; ++u) gather_slices<N, R, T>(cp, ik[u], vl[u], q, w[u]);
       const bool seg_end = t0 + P * U >= S.len;
       const Seg& Sn = seg_end ? Sq : S;
       Trip<N, P> nxt;
       load_trip<N, P, MODE == 2>(nxt, Sn, seg_end ? 0 : t0 + P * U, lane, idx, nnz, xs, perm);
-      floatx4 crow_n = crow;
-      float arow_n[GJ];
+      float crow_n[V], arow_n[GJ];
+#pragma unroll
+      for (int c = 0; c < V; ++c) crow_n[c] = crow[c];
 #pragma unroll
       for (int u = 0; u < GJ; ++u) arow_n[u] = arow[u];
       if (seg_end) row_loads(Sq, crow_n, arow_n);
@@ -930,38 +965,40 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
           d = vl[u] ? xv[u] : 0.f;
         } else {
           float xh = crow[0] * w[u][0];
-          xh = fmaf(crow[1], w[u][1], xh);
-          xh = fmaf(crow[2], w[u][2], xh);
-          xh = fmaf(crow[3], w[u][3], xh);
+#pragma unroll
+          for (int c = 1; c < V; ++c) xh = fmaf(crow[c], w[u][c], xh);
           xh = group_sum<QL>(xh);
           d = vl[u] ? (MODE == 0 ? xv[u] - xh : xh - xv[u]) : 0.f;
         }
-        acc[0] = fmaf(d, w[u][0], acc[0]);
-        acc[1] = fmaf(d, w[u][1], acc[1]);
-        acc[2] = fmaf(d, w[u][2], acc[2]);
-        acc[3] = fmaf(d, w[u][3], acc[3]);
+#pragma unroll
+        for (int c = 0; c < V; ++c) acc[c] = fmaf(d, w[u][c], acc[c]);
       }
       if (seg_end) {
 #pragma unroll
         for (int off = QL; off < 64; off <<= 1)
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[c] += __shfl_xor(acc[c], off);
-        if (tseg && slot == 0) *reinterpret_cast<floatx4*>(tseg + sg * R + 4 * q) = acc;
+          for (int c = 0; c < V; ++c) acc[c] += __shfl_xor(acc[c], off);
+        if (tseg && slot == 0)
+#pragma unroll
+          for (int c = 0; c < V; ++c) tseg[sg * R + V * q + c] = acc[c];
 #pragma unroll
         for (int u = 0; u < GJ; ++u) {
           const int j = slot + P * u;
           if (j < J)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) Gp[u][c] = fmaf(arow[u], acc[c], Gp[u][c]);
+            for (int c = 0; c < V; ++c) Gp[u][c] = fmaf(arow[u], acc[c], Gp[u][c]);
         }
         sg += nw;
         if (sg >= nseg) break;
         S = Sq;
         Sq = sg + nw < nseg ? segs[sg + nw] : none;
-        crow = crow_n;
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          crow[c] = crow_n[c];
+          acc[c] = 0.f;
+        }
 #pragma unroll
         for (int u = 0; u < GJ; ++u) arow[u] = arow_n[u];
-        acc = floatx4{0.f, 0.f, 0.f, 0.f};
         t0 = 0;
       } else {
         t0 += P * U;
@@ -974,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
     const int j = slot + P * u;
     if (j < J)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) red[wave][j * R + 4 * q + c] = Gp[u][c];
+      for (int c = 0; c < V; ++c) red[wave][j * R + V * q + c] = Gp[u][c];
   }
   __syncthreads();
   for (int e = threadIdx.x; e < J * R; e += 256)
@@ -1096,7 +1133,8 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
                                               const float* __restrict__ val, CPtrs<N, T> cp,
                                               const T* __restrict__ Cm, double* __restrict__ dpart,
                                               const int32_t* __restrict__ perm, float* __restrict__ out) {
-  constexpr int QL = R / 4;
+  constexpr int V = vpl<T>();
+  constexpr int QL = R / V;
   constexpr int P = 64 / QL;
   constexpr int U = trip_unroll<N>();
   __shared__ double red[4];
@@ -1110,7 +1148,8 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
     const Seg none{0, 0, 0};
     Seg S = segs[sg];
     Seg Sq = sg + nw < nseg ? segs[sg + nw] : none;
-    floatx4 crow = load4(Cm + (int64_t)S.row * R + 4 * q);
+    float crow[V];
+    load16(Cm + (int64_t)S.row * R + V * q, crow);
     Trip<N, P> cur;
     load_trip<N, P, false>(cur, S, 0, lane, idx, nnz, val, nullptr);
     int t0 = 0;
@@ -1123,20 +1162,25 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
         trip_elem<N, P, u>(cur, slot, ik[u], xv[u]);
         vl[u] = t0 + u * P + slot < S.len;
       });
-      floatx4 w[U];
+      float w[U][V];
 #pragma unroll
-      for (int u = 0; u < U; ++u) w[u] = gather_row_product<N, R, T>(cp, ik[u], vl[u], q);
+      for (int u = 0; u < U; ++u) gather_slices<N, R, T>(cp, ik[u], vl[u], q, w[u]);
       const bool seg_end = t0 + P * U >= S.len;
       const Seg& Sn = seg_end ? Sq : S;
       Trip<N, P> nxt;
       load_trip<N, P, false>(nxt, Sn, seg_end ? 0 : t0 + P * U, lane, idx, nnz, val, nullptr);
-      const floatx4 crow_n = seg_end ? load4(Cm + (int64_t)Sq.row * R + 4 * q) : crow;
+      float crow_n[V];
+      if (seg_end) {
+        load16(Cm + (int64_t)Sq.row * R + V * q, crow_n);
+      } else {
+#pragma unroll
+        for (int c = 0; c < V; ++c) crow_n[c] = crow[c];
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         float xh = crow[0] * w[u][0];
-        xh = fmaf(crow[1], w[u][1], xh);
-        xh = fmaf(crow[2], w[u][2], xh);
-        xh = fmaf(crow[3], w[u][3], xh);
+#pragma unroll
+        for (int c = 1; c < V; ++c) xh = fmaf(crow[c], w[u][c], xh);
         xh = group_sum<QL>(xh);
         if (vl[u] && q == 0) {
           const float e = xv[u] - xh;
@@ -1153,7 +1197,8 @@ __global__ __launch_bounds__(256) void k_loss(const Seg* __restrict__ segs, int6
       } else {
         t0 += P * U;
       }
-      crow = crow_n;
+#pragma unroll
+      for (int c = 0; c < V; ++c) crow[c] = crow_n[c];
       cur = nxt;
     }
   }
