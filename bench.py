@@ -230,7 +230,7 @@ def main():
     counts = [np.bincount(c[m], minlength=w.dims[m]) for m in range(N)]
     infos = [plan.mode_info(m) for m in range(N)]
     fibers = [info["fibers"] if info["fiber_shared"] else None for info in infos]
-    alg = algorithmic(w, nnz, counts, args.head or args.chunk or 512, fibers)
+    alg = algorithmic(w, nnz, counts, args.head or 2 * (args.chunk or 512), fibers)
     kernels = {}
     for k, (ms, n) in prof.items():
         if n == 0:

@@ -71,7 +71,7 @@ typedef struct {
   int32_t chunk;                /* elements per chunk map of a long row (0: 512) */
   int32_t head;                 /* rows of at most this many elements are updated as one serial chain; a
                                    longer row has its first `head` elements updated in place and the rest
-                                   cut into chunks (0: chunk) */
+                                   cut into chunks (0: 2 chunk) */
   int32_t fanin;                /* chunk maps folded per combine step (0 or above the maximum: 16 for
                                    J <= 16, 8 above); a row with at most fanin maps has them applied in
                                    sequence to its first chunk's result */

@@ -101,7 +101,7 @@ struct ft_plan {
   ft_desc desc{};
   int N = 0, J = 0, R = 0;
   int64_t nnz = 0;
-  int chunk = 512, head = 512, fanin = 16;
+  int chunk = 512, head = 1024, fanin = 16;
   bool no_c_cache = false;  // FT_NO_C_CACHE
   std::vector<ft::ModeMeta> meta;
   std::vector<ft::ModeHost> host;

@@ -416,52 +416,82 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
   int maxlen = it.len;
   maxlen = max(maxlen, __shfl_xor(maxlen, 16));
   maxlen = max(maxlen, __shfl_xor(maxlen, 32));
-  for (int t0 = 0; t0 < maxlen; t0 += 16) {
-    // past the end: clamp to the item's last element (valid address); those
-    // steps are neutralised below (w = 0, no decay)
+  // Software pipeline over batches of 16 elements: while the 16 dependent
+  // steps of batch b run, the gathers of batch b + 1 and the index loads of
+  // batch b + 2 are in flight, so a long serial item waits on arithmetic, not
+  // on memory.  Past the end, positions clamp to the item's last element (a
+  // valid address) and steps are neutralised (w = 0, no decay).
+  constexpr int WD = FIB ? E : RE;
+  constexpr int NI = N > 1 ? N - 1 : 1;
+  auto stage_a = [&](int t0, float& xv, int (&ix)[NI]) {
     const int64_t p = it.start + min(t0 + l, max(it.len - 1, 0));
-    const float xv = it.len > 0 ? val[p] : 0.f;
-    // phase 1: w of the 16 elements (or, with fibers, their precomputed g)
-    float w[16][FIB ? E : RE];
+    xv = it.len > 0 ? val[p] : 0.f;
     if constexpr (FIB) {
-      const int fv = it.len > 0 ? fid[p] : 0;
+      ix[0] = it.len > 0 ? fid[p] : 0;
+    } else {
+#pragma unroll
+      for (int k = 0; k < N - 1; ++k)
+        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (NC ? 1 : (int)(R * sizeof(T))) : 0;
+    }
+  };
+  auto stage_b = [&](int t0, const int (&ix)[NI], float (&w)[16][WD]) {
+    if constexpr (FIB) {
       static_for<0, 16>([&](auto S) {
         constexpr int s = decltype(S)::value;
-        const int64_t fb = (int64_t)bcast16i<s>(fv) * J;
+        const int64_t fb = (int64_t)bcast16i<s>(ix[0]) * J;
         const bool sv = (t0 + s) < it.len;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          // unconditional load (fv is a valid fiber, the column clamped) so
-          // that all 16 loads are in flight together; masked afterwards
+          // unconditional load (a valid fiber, the column clamped) so that all
+          // 16 loads are in flight together; masked afterwards
           const int j = l + 16 * e;
           const float gv = gfib[fb + min(j, J - 1)];
           w[s][e] = (sv && j < J) ? gv : 0.f;
         }
       });
+    } else if constexpr (NC) {
+      gather_w_nc<N>(nc, Bc, ix, l, t0, it.len, w);
     } else {
-      int ix[N - 1];
-#pragma unroll
-      for (int k = 0; k < N - 1; ++k)
-        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (NC ? 1 : (int)(R * sizeof(T))) : 0;
-      if constexpr (NC)
-        gather_w_nc<N>(nc, Bc, ix, l, t0, it.len, w);
-      else
-        gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
+      gather_w<N, R, T>(cp, ix, l, t0, it.len, w);
+    }
+  };
+  // (high orders keep one batch in registers: two would spill)
+  constexpr bool PIPE = (N - 1) * WD <= 4;
+  float xv0, xv1 = 0.f;
+  int ix1[NI];
+  float w0[16][WD];
+  if constexpr (PIPE) {
+    int ix0[NI];
+    stage_a(0, xv0, ix0);
+    stage_b(0, ix0, w0);
+    stage_a(16, xv1, ix1);
+  }
+  for (int t0 = 0; t0 < maxlen; t0 += 16) {
+    float wn[16][WD];
+    float xv2 = 0.f;
+    int ix2[NI];
+    if constexpr (PIPE) {
+      stage_b(t0 + 16, ix1, wn);
+      stage_a(t0 + 32, xv2, ix2);
+    } else {
+      int ixc[NI];
+      stage_a(t0, xv0, ixc);
+      stage_b(t0, ixc, w0);
     }
     static_for<0, 16>([&](auto S) {
       constexpr int s = decltype(S)::value;
       float g[E];
       if constexpr (FIB) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) g[e] = w[s][e];
+        for (int e = 0; e < E; ++e) g[e] = w0[s][e];
       } else {
-        shared_g<J, R>(Bw, w[s], g);
+        shared_g<J, R>(Bw, w0[s], g);
       }
       float pr = 0.f;
 #pragma unroll
       for (int e = 0; e < E; ++e) pr = fmaf((float)a[e], g[e], pr);
       pr = group_sum<16>(pr);
-      const float es = bcast16<s>(xv) - pr;
+      const float es = bcast16<s>(xv0) - pr;
       const double dec = (t0 + s) < it.len ? (double)c1 : 0.0;
       const double le = (double)(lr * es);
 #pragma unroll
@@ -470,6 +500,16 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
         a[e] = fma(le, (double)g[e], a[e]);
       }
     });
+    if constexpr (PIPE) {
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+#pragma unroll
+        for (int e = 0; e < WD; ++e) w0[s][e] = wn[s][e];
+      xv0 = xv1;
+      xv1 = xv2;
+#pragma unroll
+      for (int k = 0; k < NI; ++k) ix1[k] = ix2[k];
+    }
   }
   if (it.len > 0) {
 #pragma unroll

@@ -348,7 +348,7 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
   P->R = d->R;
   P->nnz = nnz;
   P->chunk = d->chunk ? d->chunk : 512;
-  P->head = d->head ? d->head : P->chunk;
+  P->head = d->head ? d->head : 2 * P->chunk;
   P->no_c_cache = (d->flags & FT_NO_C_CACHE) != 0;
   P->fanin = std::min(d->fanin ? d->fanin : max_fanin(d->J[0]), max_fanin(d->J[0]));
   try {

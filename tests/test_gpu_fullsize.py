@@ -29,7 +29,7 @@ def netflix():
     return w, c, v, A, B, plan, prm
 
 
-def _sample_rows(counts, chunk=512, head=512):
+def _sample_rows(counts, chunk=512, head=1024):
     """The longest rows and rows near the piece boundaries of the default plan (head, then chunks)."""
     order = np.argsort(-counts, kind="stable")
     picks = [order[0], order[min(5, len(order) - 1)]]

@@ -16,7 +16,7 @@ from tests.gpu_common import bf16_scale, delta_ok, to_np
 pytestmark = pytest.mark.gpu
 
 
-def _sample_rows(counts, chunk=512, head=512, max_len=None):
+def _sample_rows(counts, chunk=512, head=1024, max_len=None):
     """The longest rows and rows near the piece boundaries of the default plan (head, then chunks)."""
     order = np.argsort(-counts, kind="stable")
     if max_len is not None:
