@@ -395,12 +395,9 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
   static_assert(!NC || (J == 16 && R == 16 && !FIB), "the no-C-cache variant is built for J = R = 16");
   float Bc[N > 1 ? N - 1 : 1][16];
   if constexpr (NC) load_nc_cols<N>(nc, l, Bc);
-  // Persistent groups: the four groups of a wavefront take four consecutive
-  // items (similar lengths, the lists are sorted) and then stride by the grid,
-  // so B(m) is loaded once per group.  The trip count is wave-uniform.
-  const int64_t G = (int64_t)gridDim.x * 16;
-  for (int64_t base = (int64_t)blockIdx.x * 16 + ((threadIdx.x >> 6) << 2); base < n_items; base += G) {
-  const int64_t gid = base + ((threadIdx.x >> 4) & 3);
+  // One item per 16-lane group: the four groups of a wavefront take four
+  // consecutive items (similar lengths, the lists are sorted).
+  const int64_t gid = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
   FItem it{0, 0, 0, 0, 0};
   if (gid < n_items) it = items[gid];
   // The row is carried in FP64 registers and rounded to FP32 once when
@@ -523,7 +520,6 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
       }
     }
   }
-  }
 }
 
 // Chunk maps.  With rho = 1 - lr lam and gp = lr / rho, one step is
@@ -554,12 +550,9 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
   static_assert(!NC || (J == 16 && R == 16 && !FIB), "the no-C-cache variant is built for J = R = 16");
   float Bc[N > 1 ? N - 1 : 1][16];
   if constexpr (NC) load_nc_cols<N>(nc, l, Bc);
-  // Persistent groups: the four groups of a wavefront take four consecutive
-  // items (similar lengths, the lists are sorted) and then stride by the grid,
-  // so B(m) is loaded once per group.  The trip count is wave-uniform.
-  const int64_t G = (int64_t)gridDim.x * 16;
-  for (int64_t base = (int64_t)blockIdx.x * 16 + ((threadIdx.x >> 6) << 2); base < n_items; base += G) {
-  const int64_t gid = base + ((threadIdx.x >> 4) & 3);
+  // One item per 16-lane group: the four groups of a wavefront take four
+  // consecutive items (similar lengths, the lists are sorted).
+  const int64_t gid = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
   FItem it{0, 0, 0, 0, 0};
   if (gid < n_items) it = items[gid];
   float Nc[E][J];
@@ -651,7 +644,6 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
       }
     }
     if (l == 0) map_scale[it.slot] = pow(rho, (double)it.len);
-  }
   }
 }
 
