@@ -879,10 +879,13 @@ __device__ __forceinline__ void gather_slices(const CPtrs<N, T>& cp, const int32
 // distinct addresses: the address units, which bound these passes, see a
 // quarter of the index loads.  Positions past the end are clamped to the
 // segment's last element (a valid address), so the loads need no branch.
+// A trip shorter than 64 elements (R = 32, or high orders) would waste most
+// of such loads, so there each lane loads its own elements' indices.
 template <int N, int P>
 struct Trip {
   static constexpr int U = trip_unroll<N>();
-  static constexpr int NL = (U * P + 63) / 64;  // element loads per lane
+  static constexpr bool PERMUTE = U * P >= 64;
+  static constexpr int NL = PERMUTE ? U * P / 64 : U;  // element loads per lane
   int32_t ik[NL][N > 1 ? N - 1 : 1];
   float xv[NL];
 };
@@ -892,9 +895,10 @@ __device__ __forceinline__ void load_trip(Trip<N, P>& L, const Seg& S, int t0, i
                                           const int32_t* __restrict__ idx, int64_t nnz, const float* __restrict__ xs,
                                           const int32_t* __restrict__ perm) {
   const int last = max(S.len - 1, 0);
+  const int slot = lane / (64 / P);
 #pragma unroll
   for (int h = 0; h < Trip<N, P>::NL; ++h) {
-    const uint32_t o = (uint32_t)min(t0 + 64 * h + lane, last);
+    const uint32_t o = (uint32_t)min(Trip<N, P>::PERMUTE ? t0 + 64 * h + lane : t0 + h * P + slot, last);
 #pragma unroll
     for (int k = 0; k < N - 1; ++k) L.ik[h][k] = (idx + (int64_t)k * nnz + S.start)[o];
     L.xv[h] = PERM ? xs[(perm + S.start)[o]] : (xs + S.start)[o];
@@ -905,11 +909,17 @@ __device__ __forceinline__ void load_trip(Trip<N, P>& L, const Seg& S, int t0, i
 template <int N, int P, int u>
 __device__ __forceinline__ void trip_elem(const Trip<N, P>& L, int slot, int32_t (&ik)[N > 1 ? N - 1 : 1],
                                           float& xv) {
-  constexpr int h = (u * P) / 64;
-  const int src = (u * P + slot) & 63;
+  if constexpr (Trip<N, P>::PERMUTE) {
+    constexpr int h = (u * P) / 64;
+    const int src = (u * P + slot) & 63;
 #pragma unroll
-  for (int k = 0; k < N - 1; ++k) ik[k] = __shfl(L.ik[h][k], src);
-  xv = __shfl(L.xv[h], src);
+    for (int k = 0; k < N - 1; ++k) ik[k] = __shfl(L.ik[h][k], src);
+    xv = __shfl(L.xv[h], src);
+  } else {
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) ik[k] = L.ik[u][k];
+    xv = L.xv[u];
+  }
 }
 
 // A wavefront walks its segments gw, gw + nw, ... trip by trip.  While the
