@@ -879,13 +879,13 @@ __device__ __forceinline__ void gather_slices(const CPtrs<N, T>& cp, const int32
 // distinct addresses: the address units, which bound these passes, see a
 // quarter of the index loads.  Positions past the end are clamped to the
 // segment's last element (a valid address), so the loads need no branch.
-// A trip shorter than 64 elements (R = 32, or high orders) would waste most
+// A trip of fewer than 32 elements (R = 32 at high orders) would waste most
 // of such loads, so there each lane loads its own elements' indices.
 template <int N, int P>
 struct Trip {
   static constexpr int U = trip_unroll<N>();
-  static constexpr bool PERMUTE = U * P >= 64;
-  static constexpr int NL = PERMUTE ? U * P / 64 : U;  // element loads per lane
+  static constexpr bool PERMUTE = U * P >= 32;
+  static constexpr int NL = PERMUTE ? (U * P + 63) / 64 : U;  // element loads per lane
   int32_t ik[NL][N > 1 ? N - 1 : 1];
   float xv[NL];
 };
