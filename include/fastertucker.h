@@ -74,7 +74,7 @@ typedef struct {
                                    cut into chunks (0: 2 chunk) */
   int32_t fanin;                /* chunk maps folded per combine step (0 or above the maximum: 16 for
                                    J <= 16, 8 above); a row with at most fanin maps has them applied in
-                                   sequence to its first chunk's result */
+                                   sequence to its head's result */
   int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM | FT_NO_FIBER_SHARE | FT_NO_C_CACHE */
 } ft_desc;
 
@@ -173,9 +173,10 @@ ft_status ft_predict(const ft_plan* plan, const ft_params* p, const int32_t* d_c
  * element x of Omega, in the plan's per-row order, with
  *     w_x = prod_{n != m} C(n)[i_n, :]   (Eq. (12)),   g_x = B(m) w_x,
  *     e = x - a.g_x,   a <- a + lr (e g_x - lam a)     (Eq. (9), (10))
- * on a = A(m)[i_m, :].  Rows are independent within the pass; rows longer
- * than the chunk length are split and the exact sequential result is
- * recovered by composing the affine maps of the chunks.  C(m) is NOT
+ * on a = A(m)[i_m, :].  Rows are independent within the pass; a row longer
+ * than the head length is updated in place for its first `head` elements,
+ * the rest is cut into chunks, and the exact sequential result is recovered
+ * by applying the chunks' affine maps in order.  C(m) is NOT
  * refreshed (call ft_refresh, or use ft_factor_epoch).
  */
 ft_status ft_factor_pass(const ft_plan* plan, const ft_params* p, int32_t mode, double lr, double lam,
@@ -240,7 +241,7 @@ ft_status ft_grad(const ft_plan* plan, const ft_params* p, const float* d_upstre
  */
 typedef enum {
   FT_K_FACTOR_COMPOSE = 0, /* chunk maps of long rows */
-  FT_K_FACTOR_APPLY = 1,   /* short rows and first chunks, applied in place */
+  FT_K_FACTOR_APPLY = 1,   /* short rows and heads of long rows, applied in place */
   FT_K_COMBINE = 2,        /* folds of chunk maps */
   FT_K_REFRESH = 3,        /* C = A B */
   FT_K_SEGSUM = 4,         /* core and gradient segment sums */

@@ -1352,8 +1352,8 @@ CPtrs<N, T> others(const ft_params* p, int m) {
 }
 
 // Workgroups that fit on the device at once for a 256-thread kernel (from the
-// occupancy query, cached per kernel).  Persistent grids use at most this
-// many, so that no workgroup starts after the others have finished.
+// occupancy query, cached per kernel).  The segment passes, whose wavefronts
+// each walk a fixed set of segments, launch at most this many.
 int resident_blocks(const void* kernel) {
   static std::mutex mu;
   static std::unordered_map<const void*, int> cache;
@@ -1373,7 +1373,7 @@ int resident_blocks(const void* kernel) {
 }
 
 // One item per 16-lane group: the hardware dispatcher balances the items
-// (measured faster than a resident persistent grid for these kernels).
+// (measured faster than a grid-stride loop, which also costs registers).
 unsigned factor_blocks(const void* kernel, int64_t n_items) {
   (void)kernel;
   return (unsigned)std::max<int64_t>(1, (n_items + 15) / 16);
