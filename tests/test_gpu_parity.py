@@ -261,3 +261,24 @@ def test_no_c_cache_variant(case):
         assert ok, (name, "core", m, err, bound)
         ft.refresh(plan, prm, m)
         orc.refresh(m)
+
+
+@pytest.mark.parametrize("head", [1, 7, 1 << 30])
+def test_factor_pass_head_lengths(head):
+    """Rows split after `head` serial elements (1: every row of two or more elements is heavy; 2^30: none is)."""
+    import paper_2210_06014_amd as ft
+
+    dims, J, R = [300, 40, 12], 16, 16
+    c, v, A, B = make_problem(dims, 30_000, 1.1, J, R, seed=23)
+    plan, prm = gpu_setup(dims, J, R, c, v, A, B, chunk=16, head=head, fanin=3)
+    heavy = [plan.mode_info(m)["heavy_rows"] for m in range(3)]
+    assert (sum(heavy) == 0) == (head == 1 << 30)
+    orc = oracle_model(dims, J, R, c, v, A, B)
+    for m in range(3):
+        before = orc.A[m].copy()
+        ft.factor_pass(plan, prm, m, 1e-3, 1e-2)
+        orc.factor_pass(m, 1e-3, 1e-2)
+        ok, err, bound = delta_ok(to_np(prm.A[m]), orc.A[m], before)
+        assert ok, (head, m, err, bound)
+        ft.refresh(plan, prm, m)
+        orc.refresh(m)
