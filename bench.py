@@ -142,6 +142,55 @@ def copy_calibration(nbytes):
           flush=True)
 
 
+def curve(args):
+    """Convergence run (the analogue of the paper's Figure 3): train on 90 % of a planted tensor, report the
+    training RMSE and the held-out RMSE and MAE after every iteration, one JSON line each."""
+    import numpy as np
+    import torch
+
+    import paper_2210_06014_amd as ft
+    import synth
+
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]
+    nnz = w.nnz if args.nnz is None else args.nnz
+    lr = w.lr if args.lr is None else args.lr
+    c, v, A, B = synth.make(w, nnz=nnz)
+    test = synth.test_mask(nnz, w.seed)
+    ctr, vtr = np.ascontiguousarray(c[:, ~test]), np.ascontiguousarray(v[~test])
+    cte = torch.from_numpy(np.ascontiguousarray(c[:, test])).cuda()
+    vte = v[test].astype(np.float64)
+    N, J, R = len(w.dims), w.J[0], w.R
+    plan = ft.Plan(w.dims, J, R, ctr, vtr, chunk=args.chunk, head=args.head)
+    prm = ft.Params(A, B, storage=args.storage)
+    ft.refresh(plan, prm)
+
+    def report(epoch, ms):
+        train = float(ft.loss(plan, prm)[1].item())
+        xh = ft.predict(plan, prm, cte).double().cpu().numpy()
+        err = xh - vte
+        line = {"epoch": epoch, "storage": args.storage, "train_rmse": train,
+                "test_rmse": float(np.sqrt(np.mean(err * err))), "test_mae": float(np.mean(np.abs(err))),
+                "ms_per_iteration": ms}
+        print(json.dumps(line), flush=True)
+        return line
+
+    report(0, 0.0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    last = None
+    for ep in range(1, args.curve + 1):
+        e0.record()
+        ft.epoch(plan, prm, lr, w.lam, lr, w.lam)
+        e1.record()
+        torch.cuda.synchronize()
+        last = report(ep, e0.elapsed_time(e1))
+    summary = {"curve": args.workload, "storage": args.storage, "epochs": args.curve, "train_elements": int(vtr.size),
+               "test_elements": int(vte.size), "lr": lr, "lam": w.lam, "sigma": w.sigma, "J": J, "R": R,
+               "final_test_rmse": last["test_rmse"], "final_test_mae": last["test_mae"],
+               "test_rmse_of_the_mean": float(np.sqrt(np.mean((vte - vtr.mean()) ** 2)))}
+    print(json.dumps(summary), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,11 +210,17 @@ def main():
                     help="form g = B(m) w per element instead of once per mode-m fiber (Section 3.2 ablation)")
     ap.add_argument("--no-c-cache", action="store_true",
                     help="factor and core passes form C rows from A and B on use (FastTucker's cost; Table 5 ablation)")
+    ap.add_argument("--curve", type=int, default=0,
+                    help="convergence run instead of the benchmark: this many iterations on a planted tensor "
+                    "(e.g. --workload planted), printing train RMSE and held-out RMSE/MAE per iteration")
+    ap.add_argument("--lr", type=float, default=None, help="learning rate of a convergence run (default: workload's)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
     if args.copy_bytes:
         return copy_calibration(args.copy_bytes)
+    if args.curve:
+        return curve(args)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

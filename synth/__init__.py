@@ -114,6 +114,25 @@ def uniform_index(count: int, n: int, seed: int, tag: int) -> np.ndarray:
     return out
 
 
+def planted(coords_, dims, seed: int, noise: float = 0.25):
+    """Values of a planted separable model, for convergence runs with a held-out test set:
+    x = 1 + 4 prod_n u_n[i_n] + N(0, noise^2), clipped to [1, 5], with u_n[i] uniform in [0.3, 1)
+    drawn per index of every mode.  Real structure that a low-rank model can learn, unlike the
+    independent values of 'int1to5'."""
+    order = len(dims)
+    prod = np.ones(coords_.shape[1], dtype=np.float64)
+    for n in range(order):
+        u = 0.3 + 0.7 * uniform_index(int(dims[n]), 1 << 20, seed, 100 + n).astype(np.float64) / float(1 << 20)
+        prod *= u[coords_[n]]
+    eps = normal((coords_.shape[1],), 0.0, noise, seed, 200).astype(np.float64)
+    return np.clip(1.0 + 4.0 * prod + eps, 1.0, 5.0).astype(np.float32)
+
+
+def test_mask(nnz: int, seed: int, percent: int = 10):
+    """Seeded held-out split: True for about `percent` % of the elements."""
+    return uniform_index(int(nnz), 100, seed, 300) < percent
+
+
 def init_params(dims, J, R: int, sigma: float, seed: int):
     """A(n) (I_n x J_n) and B(n) (J_n x R), entries N(0, sigma^2) rounded to float32."""
     order = len(dims)
@@ -154,6 +173,10 @@ WORKLOADS = {
 for _n in range(3, 11):
     WORKLOADS[f"sweep_order{_n}"] = Workload(f"sweep_order{_n}", [10_000] * _n, 100_000_000, 0.0, "int1to5",
                                              [32] * _n, 32)
+# Convergence runs (the analogue of the paper's Figure 3): a Netflix-like shape with planted values
+# and a held-out test set.
+WORKLOADS["planted"] = Workload("planted", [100_000, 10_000, 1_000], 20_000_000, 1.1, "planted", [16] * 3, 16,
+                                sigma=0.3, lr=1e-2, lam=1e-2)
 for _m in (20, 40, 60, 80, 100):
     WORKLOADS[f"sweep_density{_m}"] = Workload(f"sweep_density{_m}", [1_000] * 3, _m * 1_000_000, 0.0, "int1to5",
                                                [32] * 3, 32)
@@ -164,6 +187,6 @@ def make(w: Workload, nnz: int | None = None, dims=None):
     dims = list(w.dims if dims is None else dims)
     nnz = int(w.nnz if nnz is None else nnz)
     c, _ = coords(dims, nnz, w.zipf, w.seed)
-    v = values(nnz, w.value_kind, w.seed)
+    v = planted(c, dims, w.seed) if w.value_kind == "planted" else values(nnz, w.value_kind, w.seed)
     A, B = init_params(dims, w.J, w.R, w.sigma, w.seed + 1)
     return c, v, A, B

@@ -78,3 +78,23 @@ def test_values_and_params():
     assert abs(A[0].std() - 0.1) < 0.005 and abs(A[0].mean()) < 0.005
     A2, _ = synth.init_params([1000, 30], 8, 4, 0.1, seed=4)
     np.testing.assert_array_equal(A[0], A2[0])
+
+
+def test_planted_values_and_split():
+    """Planted values: seeded, in [1, 5], a separable signal with noise; the held-out split takes about 10 %."""
+    dims = [500, 60, 7]
+    c, _ = synth.coords(dims, 20_000, 1.1, seed=4)
+    v1 = synth.planted(c, dims, seed=4)
+    v2 = synth.planted(c, dims, seed=4)
+    assert v1.dtype == np.float32 and np.array_equal(v1, v2)
+    assert v1.min() >= 1.0 and v1.max() <= 5.0
+    # without noise the values are 1 + 4 prod_n u_n with u_n in [0.3, 1)
+    v0 = synth.planted(c, dims, seed=4, noise=0.0)
+    assert v0.min() >= 1.0 + 4 * 0.3 ** 3 - 1e-5 and v0.max() < 5.0
+    # the signal depends on the coordinates: equal coordinates give equal noiseless values
+    order = np.lexsort(c[::-1])
+    cs, vs = c[:, order], v0[order]
+    same = np.all(cs[:, 1:] == cs[:, :-1], axis=0)
+    assert np.all(vs[1:][same] == vs[:-1][same])
+    m = synth.test_mask(200_000, seed=1)
+    assert 0.09 < m.mean() < 0.11
