@@ -103,12 +103,22 @@ def cpu_baseline(w, c, v, A, B, sample):
 
 
 COUNTER_FILES = {"netflix": "profiles/netflix_j16_fp32_hbm_counters.md"}
+KERNEL_SOURCES = ["ft_device.h", "ft_refresh.hip", "ft_factor.hip", "ft_segment.hip"]
+
+
+def kernel_sources_sha256():
+    """sha256 over the device sources, in KERNEL_SOURCES order (recorded with the counter summaries)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2210_06014_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
 
 
 def counter_traffic(workload, kernel):
     """Measured HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when
     there is none for this workload or the kernel source has changed since the counters were taken."""
-    import hashlib
     import re
 
     path = COUNTER_FILES.get(workload)
@@ -118,8 +128,7 @@ def counter_traffic(workload, kernel):
     if not m:
         return None
     data = json.loads(m.group(1))
-    src = os.path.join(ROOT, "paper_2210_06014_amd", "csrc", "ft_kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != data.get("kernels_sha256"):
+    if kernel_sources_sha256() != data.get("kernels_sha256"):
         return None
     return data["traffic_bytes_per_launch"].get(kernel)
 

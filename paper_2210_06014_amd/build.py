@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfastertucker.so")
-SOURCES = ["ft_plan.cpp", "ft_api.cpp", "ft_kernels.hip"]
+SOURCES = ["ft_plan.cpp", "ft_api.cpp", "ft_refresh.hip", "ft_factor.hip", "ft_segment.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -128,7 +128,7 @@ namespace ft {
 void set_error(const std::string& msg);
 ft_status fail(ft_status s, const std::string& msg);
 
-// kernel launchers (ft_kernels.hip); return hipSuccess or the launch error
+// kernel launchers (ft_refresh.hip, ft_factor.hip, ft_segment.hip); return hipSuccess or the launch error
 constexpr int kPartials = 2048;  // max workgroups of the reduction kernels
 constexpr int kSegLen = 512;     // max elements per segment
 
