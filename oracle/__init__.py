@@ -45,6 +45,8 @@ def _load():
         lib.orc_predict.restype = None
         lib.orc_factor_pass.argtypes = [i32, vp, vp, i32, vp, vp, vp, vp, vp, i64, i32, dbl, dbl]
         lib.orc_factor_pass.restype = i32
+        lib.orc_factor_pass_relaxed.argtypes = [i32, vp, vp, i32, vp, vp, vp, vp, vp, i64, i32, dbl, dbl, i64, i64]
+        lib.orc_factor_pass_relaxed.restype = i32
         lib.orc_core_grad.argtypes = [i32, vp, i32, vp, vp, vp, vp, vp, i64, i32, vp]
         lib.orc_core_grad.restype = i32
         lib.orc_core_pass.argtypes = [i32, vp, i32, vp, vp, vp, vp, vp, i64, i32, dbl, dbl]
@@ -108,6 +110,24 @@ class Model:
                                      _p(self.vals), self.nnz, int(m), float(lr), float(lam))
         if rc:
             raise RuntimeError(f"orc_factor_pass: {rc}")
+
+    def factor_pass_relaxed(self, m, lr, lam, head, chunk):
+        """Relaxed factor module for mode m (stale chunk reads of Algorithm 4, merged with a step guard;
+        no refresh of C(m)).  The reading is stated in ft_oracle.c."""
+        rc = _load().orc_factor_pass_relaxed(*self._common(), _parr(self.A), _parr(self.B), _parr(self.C),
+                                             _p(self.coords), _p(self.vals), self.nnz, int(m), float(lr), float(lam),
+                                             int(head), int(chunk))
+        if rc:
+            raise RuntimeError(f"orc_factor_pass_relaxed: {rc}")
+
+    def epoch_relaxed(self, lr_a, lam_a, lr_b, lam_b, head, chunk):
+        """One iteration of Algorithm 2 with the relaxed factor module."""
+        for m in range(self.N):
+            self.factor_pass_relaxed(m, lr_a, lam_a, head, chunk)
+            self.refresh(m)
+        for m in range(self.N):
+            self.core_pass(m, lr_b, lam_b)
+            self.refresh(m)
 
     def core_grad(self, m) -> np.ndarray:
         """G = sum_x e_x a_{i_m} w_x^T over Omega (Eq. (11), Algorithm 5)."""

@@ -154,6 +154,113 @@ int orc_factor_pass(int N, const int64_t* dims, const int* Jv, int R, double* co
   return ORC_OK;
 }
 
+/* ---- row order of the relaxed pass: i_m first, then the fiber order ---- */
+static int cmp_row(const void* pa, const void* pb) {
+  int64_t a = *(const int64_t*)pa, b = *(const int64_t*)pb;
+  for (int k = 0; k < g_N; ++k) {
+    int n = (g_m + k) % g_N;
+    int32_t ia = g_coords[n * g_stride + a], ib = g_coords[n * g_stride + b];
+    if (ia != ib) return ia < ib ? -1 : 1;
+  }
+  return (a > b) - (a < b);
+}
+
+/* one SGD step of Eq. (9)/(10) on a, returns ||g||^2 */
+static double sgd_step(int N, int m, int J, int R, const double* Bm, const double* const* C, const int32_t* coords,
+                       const double* vals, int64_t nnz, int64_t x, double lr, double lam, double* a, double* w,
+                       double* g) {
+  fiber_w_g(N, m, J, R, Bm, C, coords, nnz, x, w, g);
+  double xhat = 0.0, gg = 0.0;
+  for (int j = 0; j < J; ++j) {
+    xhat += a[j] * g[j];
+    gg += g[j] * g[j];
+  }
+  double e = vals[x] - xhat;
+  for (int j = 0; j < J; ++j) a[j] = a[j] + lr * (e * g[j] - lam * a[j]);
+  return gg;
+}
+
+/*
+ * Relaxed factor module for mode m: a deterministic model of the concurrent
+ * row updates of the GPU factor algorithm (Algorithm 4 lets many workers read
+ * and write one row without ordering).  This is a reading of that algorithm,
+ * not the serial result of Algorithm 2.
+ *
+ * A row's elements are taken in the order i_m, i_{m+1}, ..., i_{m-1} (the
+ * per-row order of the fiber traversal).  A row of at most `head` elements is
+ * updated serially, exactly as in orc_factor_pass.  A longer row:
+ *   - its first `head` elements update the row serially: a_H;
+ *   - the rest is cut into chunks of `chunk` elements; every chunk k runs its
+ *     steps serially from the row's value a0 at the start of the pass (a stale
+ *     read), reaching a_k after L_k steps.  Its increment beyond the decay of
+ *     a0 is d_k = a_k - rho^{L_k} a0, with rho = 1 - lr lam;
+ *   - the increments are merged in the order of the chunks, each decayed by
+ *     the steps that follow it: S = sum_k rho^{T_k} d_k, where T_k counts the
+ *     row's elements after chunk k;
+ *   - guard: with G = sum of ||g||^2 over the chunked elements,
+ *     omega = min(1, 1 / (lr G)), and the row becomes
+ *         a = rho^{L - head} a_H + omega S.
+ * If the chunk steps did not depend on the row (g g^T a dropped from the
+ * step), this would be the serial result exactly; as it is, it differs from
+ * the serial result by O(lr^2) while omega = 1.  The guard keeps the merged
+ * linearised step I - lr omega sum g g^T between 0 and I, so the summed
+ * stale increments cannot overshoot when many chunks fit the same row.
+ */
+int orc_factor_pass_relaxed(int N, const int64_t* dims, const int* Jv, int R, double* const* A,
+                            const double* const* B, const double* const* C, const int32_t* coords, const double* vals,
+                            int64_t nnz, int m, double lr, double lam, int64_t head, int64_t chunk) {
+  (void)dims;
+  if (N < 2 || m < 0 || m >= N || head < 0 || chunk < 1) return ORC_ERR_ARG;
+  int J = Jv[m];
+  double* Am = A[m];
+  const double* Bm = B[m];
+  const double rho = 1.0 - lr * lam;
+  int64_t* ord = (int64_t*)malloc(sizeof(int64_t) * (nnz > 0 ? nnz : 1));
+  double* w = (double*)malloc(sizeof(double) * R);
+  double* g = (double*)malloc(sizeof(double) * J);
+  double* a0 = (double*)malloc(sizeof(double) * J);
+  double* b = (double*)malloc(sizeof(double) * J);
+  double* S = (double*)malloc(sizeof(double) * J);
+  if (!ord || !w || !g || !a0 || !b || !S) {
+    free(ord); free(w); free(g); free(a0); free(b); free(S);
+    return ORC_ERR_NOMEM;
+  }
+  for (int64_t x = 0; x < nnz; ++x) ord[x] = x;
+  g_N = N;
+  g_m = m;
+  g_coords = coords;
+  g_stride = nnz;
+  qsort(ord, (size_t)nnz, sizeof(int64_t), cmp_row);
+  int64_t p = 0;
+  while (p < nnz) {
+    int32_t row = coords[m * nnz + ord[p]];
+    int64_t q = p;
+    while (q < nnz && coords[m * nnz + ord[q]] == row) ++q;
+    int64_t L = q - p;
+    double* a = Am + (int64_t)row * J;
+    for (int j = 0; j < J; ++j) a0[j] = a[j];
+    int64_t hl = L <= head ? L : head;
+    for (int64_t t = 0; t < hl; ++t) sgd_step(N, m, J, R, Bm, C, coords, vals, nnz, ord[p + t], lr, lam, a, w, g);
+    if (L > head) {
+      double G = 0.0;
+      for (int j = 0; j < J; ++j) S[j] = 0.0;
+      for (int64_t c0 = head; c0 < L; c0 += chunk) {
+        int64_t c1 = c0 + chunk < L ? c0 + chunk : L;
+        for (int j = 0; j < J; ++j) b[j] = a0[j];
+        for (int64_t t = c0; t < c1; ++t) G += sgd_step(N, m, J, R, Bm, C, coords, vals, nnz, ord[p + t], lr, lam, b, w, g);
+        double decay_own = pow(rho, (double)(c1 - c0)), decay_after = pow(rho, (double)(L - c1));
+        for (int j = 0; j < J; ++j) S[j] += decay_after * (b[j] - decay_own * a0[j]);
+      }
+      double omega = lr * G > 1.0 ? 1.0 / (lr * G) : 1.0;
+      double decay_rest = pow(rho, (double)(L - head));
+      for (int j = 0; j < J; ++j) a[j] = decay_rest * a[j] + omega * S[j];
+    }
+    p = q;
+  }
+  free(ord); free(w); free(g); free(a0); free(b); free(S);
+  return ORC_OK;
+}
+
 /*
  * Core gradient of mode m over all elements at fixed parameters
  * (Eq. (11), summed over Omega as Algorithm 5 accumulates it):
