@@ -112,8 +112,9 @@ class Model:
             raise RuntimeError(f"orc_factor_pass: {rc}")
 
     def factor_pass_relaxed(self, m, lr, lam, head, chunk):
-        """Relaxed factor module for mode m (stale chunk reads of Algorithm 4, merged with a step guard;
-        no refresh of C(m)).  The reading is stated in ft_oracle.c."""
+        """Relaxed factor module for mode m (the chunks of a long row all read the row as its head left it,
+        as concurrent workers of Algorithm 4 would; their increments are merged under a step guard).  No
+        refresh of C(m).  The reading is stated in ft_oracle.c."""
         rc = _load().orc_factor_pass_relaxed(*self._common(), _parr(self.A), _parr(self.B), _parr(self.C),
                                              _p(self.coords), _p(self.vals), self.nnz, int(m), float(lr), float(lam),
                                              int(head), int(chunk))

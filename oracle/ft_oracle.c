@@ -189,22 +189,25 @@ static double sgd_step(int N, int m, int J, int R, const double* Bm, const doubl
  * A row's elements are taken in the order i_m, i_{m+1}, ..., i_{m-1} (the
  * per-row order of the fiber traversal).  A row of at most `head` elements is
  * updated serially, exactly as in orc_factor_pass.  A longer row:
- *   - its first `head` elements update the row serially: a_H;
+ *   - its first `head` elements update the row serially, from a0 to a_H;
  *   - the rest is cut into chunks of `chunk` elements; every chunk k runs its
- *     steps serially from the row's value a0 at the start of the pass (a stale
- *     read), reaching a_k after L_k steps.  Its increment beyond the decay of
- *     a0 is d_k = a_k - rho^{L_k} a0, with rho = 1 - lr lam;
+ *     steps serially from a_H (all chunks read the row as the head left it),
+ *     reaching b_k after L_k steps.  Its increment beyond the decay of a_H is
+ *     d_k = b_k - rho^{L_k} a_H, with rho = 1 - lr lam;
  *   - the increments are merged in the order of the chunks, each decayed by
  *     the steps that follow it: S = sum_k rho^{T_k} d_k, where T_k counts the
- *     row's elements after chunk k;
+ *     row's elements after chunk k.  Without a guard the row would become
+ *     rho^{L - head} a_H + S;
  *   - guard: with G = sum of ||g||^2 over the chunked elements,
- *     omega = min(1, 1 / (lr G)), and the row becomes
- *         a = rho^{L - head} a_H + omega S.
+ *     omega = min(1, 1 / (lr G)) scales that whole step:
+ *         a = a_H + omega ((rho^{L - head} - 1) a_H + S).
  * If the chunk steps did not depend on the row (g g^T a dropped from the
- * step), this would be the serial result exactly; as it is, it differs from
- * the serial result by O(lr^2) while omega = 1.  The guard keeps the merged
- * linearised step I - lr omega sum g g^T between 0 and I, so the summed
- * stale increments cannot overshoot when many chunks fit the same row.
+ * step), the unguarded row would be the serial result exactly; as it is, it
+ * differs from the serial result by O(lr^2) while omega = 1.  To first order
+ * the merged step is lr times the row's full-batch gradient over the chunked
+ * elements; omega keeps lr omega sum g g^T below I, so the summed increments
+ * cannot overshoot when many chunks fit the same row, and since it scales
+ * the decay too, the rows it damps are not pulled towards zero.
  */
 int orc_factor_pass_relaxed(int N, const int64_t* dims, const int* Jv, int R, double* const* A,
                             const double* const* B, const double* const* C, const int32_t* coords, const double* vals,
@@ -218,11 +221,10 @@ int orc_factor_pass_relaxed(int N, const int64_t* dims, const int* Jv, int R, do
   int64_t* ord = (int64_t*)malloc(sizeof(int64_t) * (nnz > 0 ? nnz : 1));
   double* w = (double*)malloc(sizeof(double) * R);
   double* g = (double*)malloc(sizeof(double) * J);
-  double* a0 = (double*)malloc(sizeof(double) * J);
   double* b = (double*)malloc(sizeof(double) * J);
   double* S = (double*)malloc(sizeof(double) * J);
-  if (!ord || !w || !g || !a0 || !b || !S) {
-    free(ord); free(w); free(g); free(a0); free(b); free(S);
+  if (!ord || !w || !g || !b || !S) {
+    free(ord); free(w); free(g); free(b); free(S);
     return ORC_ERR_NOMEM;
   }
   for (int64_t x = 0; x < nnz; ++x) ord[x] = x;
@@ -238,26 +240,26 @@ int orc_factor_pass_relaxed(int N, const int64_t* dims, const int* Jv, int R, do
     while (q < nnz && coords[m * nnz + ord[q]] == row) ++q;
     int64_t L = q - p;
     double* a = Am + (int64_t)row * J;
-    for (int j = 0; j < J; ++j) a0[j] = a[j];
     int64_t hl = L <= head ? L : head;
     for (int64_t t = 0; t < hl; ++t) sgd_step(N, m, J, R, Bm, C, coords, vals, nnz, ord[p + t], lr, lam, a, w, g);
     if (L > head) {
+      /* a holds a_H from here on */
       double G = 0.0;
       for (int j = 0; j < J; ++j) S[j] = 0.0;
       for (int64_t c0 = head; c0 < L; c0 += chunk) {
         int64_t c1 = c0 + chunk < L ? c0 + chunk : L;
-        for (int j = 0; j < J; ++j) b[j] = a0[j];
+        for (int j = 0; j < J; ++j) b[j] = a[j];
         for (int64_t t = c0; t < c1; ++t) G += sgd_step(N, m, J, R, Bm, C, coords, vals, nnz, ord[p + t], lr, lam, b, w, g);
         double decay_own = pow(rho, (double)(c1 - c0)), decay_after = pow(rho, (double)(L - c1));
-        for (int j = 0; j < J; ++j) S[j] += decay_after * (b[j] - decay_own * a0[j]);
+        for (int j = 0; j < J; ++j) S[j] += decay_after * (b[j] - decay_own * a[j]);
       }
       double omega = lr * G > 1.0 ? 1.0 / (lr * G) : 1.0;
       double decay_rest = pow(rho, (double)(L - head));
-      for (int j = 0; j < J; ++j) a[j] = decay_rest * a[j] + omega * S[j];
+      for (int j = 0; j < J; ++j) a[j] = a[j] + omega * ((decay_rest - 1.0) * a[j] + S[j]);
     }
     p = q;
   }
-  free(ord); free(w); free(g); free(a0); free(b); free(S);
+  free(ord); free(w); free(g); free(b); free(S);
   return ORC_OK;
 }
 

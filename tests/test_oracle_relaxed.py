@@ -1,4 +1,5 @@
-"""Pins of the oracle's relaxed factor module (stale chunk reads merged with a step guard).
+"""Pins of the oracle's relaxed factor module (chunks that read a long row as its head left it,
+merged under a step guard).
 
 The relaxed module is a reading of the unordered row updates of Algorithm 4,
 not a formula the paper prints, so it is pinned by what its definition forces:
@@ -96,19 +97,21 @@ def _serial_shared_g(a, g, x, lr, lam, T):
     return rho ** T * perp + (uT / gg) * g
 
 
-@pytest.mark.parametrize("lam", [0.0, 0.3])
+@pytest.mark.parametrize("decay", [0.0, 0.02])
 @pytest.mark.parametrize("step", [0.01, 0.5])
-def test_shared_g_closed_form(step, lam):
+def test_shared_g_closed_form(step, decay):
     """On a row whose elements share g and x, T serial steps have the closed form above.  The
-    head runs from a0 to a_H; chunk k (L_k elements) runs from a0 to b_k and contributes
-    d_k = b_k - rho^{L_k} a0, decayed by rho^{T_k} for the T_k elements after it; the sum is
-    scaled by omega = min(1, 1 / (lr (L - head) |g|^2)) and added to rho^{L - head} a_H.
-    lr |g|^2 = 0.5 makes the guard act; lam = 0.3 weighs every chunk by its own decay."""
+    head runs from a0 to a_H; chunk k (L_k elements) runs from a_H to b_k and contributes
+    d_k = b_k - rho^{L_k} a_H, decayed by rho^{T_k} for the T_k elements after it; with
+    omega = min(1, 1 / (lr (L - head) |g|^2)) the row becomes
+    a_H + omega ((rho^{L - head} - 1) a_H + sum_k rho^{T_k} d_k).
+    lr |g|^2 = 0.5 makes the guard act; lr lam = 0.02 weighs every chunk by its own decay."""
     dims, J, R, c, v, A, B, g = _shared_g_row()
     head, chunk = 4, 7
     L = c.shape[1]
     gg = g @ g
     lr = step / gg
+    lam = decay / lr
     rho = 1.0 - lr * lam
     m = oracle.Model(dims, J, R, c, v, A, B)
     m.factor_pass_relaxed(0, lr, lam, head=head, chunk=chunk)
@@ -117,18 +120,39 @@ def test_shared_g_closed_form(step, lam):
     starts = list(range(head, L, chunk))
     lens = [min(chunk, L - s0) for s0 in starts]
     assert lens == [7, 7, 7, 5]
-    S = sum(rho ** (L - s0 - Lk) * (_serial_shared_g(a0, g, 3.0, lr, lam, Lk) - rho ** Lk * a0)
+    S = sum(rho ** (L - s0 - Lk) * (_serial_shared_g(a_head, g, 3.0, lr, lam, Lk) - rho ** Lk * a_head)
             for s0, Lk in zip(starts, lens))
     omega = min(1.0, 1.0 / (step * (L - head)))
     assert (omega < 0.1) == (step == 0.5)
-    want = rho ** (L - head) * a_head + omega * S
+    want = a_head + omega * ((rho ** (L - head) - 1.0) * a_head + S)
     np.testing.assert_allclose(m.A[0][0], want, rtol=1e-12)
-    if lam == 0.0:
-        # omega sum_k (1 - q^{L_k}) <= omega lr |g|^2 (L - head) <= 1 and 0 <= q^head <= 1 with
-        # q = 1 - lr |g|^2: the residual after the pass is no larger than at its start
-        e0 = 3.0 - a0 @ g
+    if decay == 0.0:
+        # chunk k moves the residual e_H by e_H (1 - q^{L_k}), q = 1 - lr |g|^2, and
+        # omega sum_k (1 - q^{L_k}) <= omega lr |g|^2 (L - head) <= 1: the residual after the
+        # pass lies between 0 and the residual after the head (no overshoot)
+        e_head = 3.0 - a_head @ g
         e_after = 3.0 - m.A[0][0] @ g
-        assert abs(e_after) <= abs(e0) * (1 + 1e-12)
+        assert abs(e_after) <= abs(e_head) * (1 + 1e-12) and e_after * e_head >= 0
+
+
+def test_guard_keeps_the_fixed_point():
+    """The guard scales the whole merged step, decay included, so a row already at the balance of
+    decay and data (here: a = 0 with x = 0) stays there, and rows damped by omega are not pulled
+    towards zero faster than the data pulls them out: on the shared-g row with x = 3, lam > 0 and
+    the guard active, a.g after the pass lies between its value after the head and the fixed point
+    u* = lr |g|^2 x / (1 - rho + lr |g|^2) of the serial steps."""
+    dims, J, R, c, v, A, B, g = _shared_g_row()
+    gg = g @ g
+    lr = 0.5 / gg
+    lam = 0.02 / lr
+    rho = 1.0 - lr * lam
+    m = oracle.Model(dims, J, R, c, v, A, B)
+    m.factor_pass_relaxed(0, lr, lam, head=4, chunk=7)
+    u_head = _serial_shared_g(A[0][0], g, 3.0, lr, lam, 4) @ g
+    u_star = lr * gg * 3.0 / (1.0 - rho + lr * gg)
+    u_after = m.A[0][0] @ g
+    lo, hi = sorted([u_head, u_star])
+    assert lo - 1e-12 <= u_after <= hi + 1e-12, (u_head, u_after, u_star)
 
 
 def test_decay_only_closed_form():
