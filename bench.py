@@ -30,12 +30,13 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic(w, nnz, row_counts, head, fibers):
+def algorithmic(w, nnz, row_counts, head, fibers, relaxed=False):
     """Per-epoch algorithmic flops and bytes per kernel family (formulas in the design notes).
 
     fibers[m] is the number of mode-m fibers when g = B(m) w is shared per fiber
     (Section 3.2), else None: a shared mode computes g once per fiber and the
-    factor kernels read it instead of forming it per element.
+    factor kernels read it instead of forming it per element.  With relaxed
+    factor passes the chunk kernel runs the plain SGD steps (no map matrix).
     """
     import numpy as np
 
@@ -67,7 +68,7 @@ def algorithmic(w, nnz, row_counts, head, fibers):
         out["factor_compose"][0] += comp * f_elem
         # executed on top: the chunk map's matrix part, a J x J matrix-vector
         # product and a rank-1 update per element (4 J^2 flops)
-        out["compose_executed"][0] += comp * (f_elem + 4 * J * J)
+        out["compose_executed"][0] += comp * (f_elem + (2 * J if relaxed else 4 * J * J))
         out["factor_compose"][1] += comp * e_bytes + c_share * comp / max(nnz, 1)
         out["factor_apply"][0] += app * f_elem
         out["factor_apply"][1] += app * e_bytes + c_share * app / max(nnz, 1) + 2 * a_bytes[m]
@@ -170,7 +171,7 @@ def curve(args):
     cte = torch.from_numpy(np.ascontiguousarray(c[:, test])).cuda()
     vte = v[test].astype(np.float64)
     N, J, R = len(w.dims), w.J[0], w.R
-    plan = ft.Plan(w.dims, J, R, ctr, vtr, chunk=args.chunk, head=args.head)
+    plan = ft.Plan(w.dims, J, R, ctr, vtr, chunk=args.chunk, head=args.head, relaxed=args.relaxed)
     prm = ft.Params(A, B, storage=args.storage)
     ft.refresh(plan, prm)
 
@@ -178,7 +179,7 @@ def curve(args):
         train = float(ft.loss(plan, prm)[1].item())
         xh = ft.predict(plan, prm, cte).double().cpu().numpy()
         err = xh - vte
-        line = {"epoch": epoch, "storage": args.storage, "train_rmse": train,
+        line = {"epoch": epoch, "storage": args.storage, "relaxed": args.relaxed, "train_rmse": train,
                 "test_rmse": float(np.sqrt(np.mean(err * err))), "test_mae": float(np.mean(np.abs(err))),
                 "ms_per_iteration": ms}
         print(json.dumps(line), flush=True)
@@ -193,7 +194,7 @@ def curve(args):
         e1.record()
         torch.cuda.synchronize()
         last = report(ep, e0.elapsed_time(e1))
-    summary = {"curve": args.workload, "storage": args.storage, "epochs": args.curve, "train_elements": int(vtr.size),
+    summary = {"curve": args.workload, "storage": args.storage, "relaxed": args.relaxed, "epochs": args.curve, "train_elements": int(vtr.size),
                "test_elements": int(vte.size), "lr": lr, "lam": w.lam, "sigma": w.sigma, "J": J, "R": R,
                "final_test_rmse": last["test_rmse"], "final_test_mae": last["test_mae"],
                "test_rmse_of_the_mean": float(np.sqrt(np.mean((vte - vtr.mean()) ** 2)))}
@@ -219,6 +220,9 @@ def main():
                     help="form g = B(m) w per element instead of once per mode-m fiber (Section 3.2 ablation)")
     ap.add_argument("--no-c-cache", action="store_true",
                     help="factor and core passes form C rows from A and B on use (FastTucker's cost; Table 5 ablation)")
+    ap.add_argument("--relaxed", action="store_true",
+                    help="relaxed factor passes: chunks of long rows read the row as it was at the start of the "
+                    "pass and their increments are merged with a step guard (FT_RELAXED)")
     ap.add_argument("--curve", type=int, default=0,
                     help="convergence run instead of the benchmark: this many iterations on a planted tensor "
                     "(e.g. --workload planted), printing train RMSE and held-out RMSE/MAE per iteration")
@@ -260,7 +264,7 @@ def main():
     log(f"generated in {time.time() - t:.1f} s")
     t = time.time()
     plan = ft.Plan(w.dims, J, R, c, v, chunk=args.chunk, head=args.head, fiber_share=not args.no_fiber_share,
-                   c_cache=not args.no_c_cache)
+                   c_cache=not args.no_c_cache, relaxed=args.relaxed)
     log(f"plan built and uploaded in {time.time() - t:.1f} s ({plan.device_bytes() / 2**30:.2f} GiB on device)")
     prm = ft.Params(A, B, storage=args.storage)
     ft.refresh(plan, prm)
@@ -294,7 +298,7 @@ def main():
     counts = [np.bincount(c[m], minlength=w.dims[m]) for m in range(N)]
     infos = [plan.mode_info(m) for m in range(N)]
     fibers = [info["fibers"] if info["fiber_shared"] else None for info in infos]
-    alg = algorithmic(w, nnz, counts, args.head or 2 * (args.chunk or 512), fibers)
+    alg = algorithmic(w, nnz, counts, args.head or 2 * (args.chunk or 512), fibers, args.relaxed)
     kernels = {}
     for k, (ms, n) in prof.items():
         if n == 0:
@@ -307,7 +311,7 @@ def main():
         flops, byts = alg.get(dom, [0.0, 0.0])
         traffic = (counter_traffic(args.workload, dom)
                    if args.nnz is None and not args.chunk and not args.head and args.storage == "f32"
-                   and not args.no_fiber_share and not args.no_c_cache
+                   and not args.no_fiber_share and not args.no_c_cache and not args.relaxed
                    else None)
         launches = kernels[dom]["launches_per_step"]
         if dom in ("factor_compose", "factor_apply"):
@@ -371,6 +375,8 @@ def main():
             "workload": f"{args.workload}: {'x'.join(map(str, w.dims))}, {nnz} distinct coordinates, "
             f"Zipf({w.zipf}) per mode, values {w.value_kind}, J={J}, R={R}, lr={w.lr}, lam={w.lam}, init N(0,{w.sigma}^2)",
             "step": "factor pass + C refresh per mode, core pass + C refresh per mode, RMSE pass",
+            "factor_passes": ("relaxed: chunks of long rows from the row at the start of the pass, guarded merge"
+                              if args.relaxed else "exact serial SGD per row"),
             "fiber_shared_modes": [m for m in range(N) if fibers[m] is not None],
             "fibers_per_mode": [info["fibers"] for info in infos],
             "rmse_start": rmse0,

@@ -60,6 +60,17 @@ typedef enum {
                                comparison of Table 5; implies FT_NO_FIBER_SHARE).  Order 3, J = R = 16 and FP32
                                storage only (FT_ERR_UNSUPPORTED otherwise); loss, predict and gradient calls
                                still read C, which the refreshes keep current */
+#define FT_RELAXED 16       /* relaxed factor passes, modelled on the unordered concurrent row updates of the
+                               GPU factor algorithm (Algorithm 4).  A row longer than `head` has its head
+                               updated in place (a_H); its chunks then all start from a_H, as concurrent
+                               workers reading the row would; chunk k's increment beyond the decay of a_H,
+                               d_k, is weighted by rho^T_k (rho = 1 - lr lam, T_k the row's elements after
+                               the chunk), and the row becomes a_H + omega ((rho^(L - head) - 1) a_H +
+                               sum_k rho^T_k d_k) with omega = min(1, 1 / (lr sum ||g||^2)) over the chunked
+                               elements, which keeps the merged step from overshooting.  Not the serial
+                               result of Algorithm 2 (it agrees to second order in lr); deterministic.  Rows
+                               of at most `head` elements are updated exactly as without the flag.  Not with
+                               FT_NO_C_CACHE (FT_ERR_UNSUPPORTED) */
 
 /* Shape of the problem and of the plan. */
 typedef struct {
@@ -75,7 +86,7 @@ typedef struct {
   int32_t fanin;                /* chunk maps folded per combine step (0 or above the maximum: 16 for
                                    J <= 16, 8 above); a row with at most fanin maps has them applied in
                                    sequence to its head's result */
-  int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM | FT_NO_FIBER_SHARE | FT_NO_C_CACHE */
+  int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM | FT_NO_FIBER_SHARE | FT_NO_C_CACHE | FT_RELAXED */
 } ft_desc;
 
 /* ft_params.storage */
@@ -240,9 +251,9 @@ ft_status ft_grad(const ft_plan* plan, const ft_params* p, const float* d_upstre
  * work with the same plan.
  */
 typedef enum {
-  FT_K_FACTOR_COMPOSE = 0, /* chunk maps of long rows */
+  FT_K_FACTOR_COMPOSE = 0, /* chunk maps of long rows (FT_RELAXED: chunk increments) */
   FT_K_FACTOR_APPLY = 1,   /* short rows and heads of long rows, applied in place */
-  FT_K_COMBINE = 2,        /* folds of chunk maps */
+  FT_K_COMBINE = 2,        /* folds of chunk maps (FT_RELAXED: the merge of the increments) */
   FT_K_REFRESH = 3,        /* C = A B */
   FT_K_SEGSUM = 4,         /* core and gradient segment sums */
   FT_K_REDUCE = 5,         /* partial-sum reduction and B step */

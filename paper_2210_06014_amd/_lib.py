@@ -12,6 +12,7 @@ FT_KEEP_HOST = 1
 FT_WITH_PERM = 2
 FT_NO_FIBER_SHARE = 4
 FT_NO_C_CACHE = 8
+FT_RELAXED = 16
 
 STATUS = {
     0: "FT_OK",

@@ -118,14 +118,22 @@ __global__ __launch_bounds__(256) void k_fiber_g(const int32_t* __restrict__ fib
   }
 }
 
-template <int N, int J, int R, class T, bool FIB, bool NC = false>
+// Heads write the row's head vector, or A(m) itself when hvec is null (the
+// relaxed passes).  With RLX the items are the chunks of long rows under
+// FT_RELAXED: each runs from the row as its head left it, a_H (in A(m); the
+// merge that follows is the only other writer) and stores its increment
+// beyond the decay of a_H, weighted by the decay of the row's later elements,
+//     rho^T (a - rho^len a_H),   T = elements of the row after the chunk,
+// and the sum of ||g||^2 over its steps, J + 1 floats per chunk slot.
+template <int N, int J, int R, class T, bool FIB, bool NC = false, bool RLX = false>
 __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ items, int64_t n_items,
                                                       const int32_t* __restrict__ idx, int64_t nnz,
                                                       const float* __restrict__ val, CPtrs<N, T> cp,
                                                       const T* __restrict__ Bm, float* __restrict__ Am,
                                                       float* __restrict__ hvec, float lr, float c1,
                                                       const int32_t* __restrict__ fid, const float* __restrict__ gfib,
-                                                      NoC<N> nc) {
+                                                      NoC<N> nc, float* __restrict__ incr,
+                                                      const int64_t* __restrict__ row_ptr, double rho) {
   constexpr int E = J >= 16 ? J / 16 : 1;
   constexpr int RE = R >= 16 ? R / 16 : 1;
   const int l = threadIdx.x & 15;
@@ -198,6 +206,7 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
   };
   // (high orders keep one batch in registers: two would spill)
   constexpr bool PIPE = (N - 1) * WD <= 4;
+  float gg = 0.f;  // sum of ||g||^2 over the steps (RLX)
   float xv0, xv1 = 0.f;
   int ix1[NI];
   float w0[16][WD];
@@ -235,6 +244,10 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
       const float es = bcast16<s>(xv0) - pr;
       const double dec = (t0 + s) < it.len ? (double)c1 : 0.0;
       const double le = (double)(lr * es);
+      if constexpr (RLX) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) gg = fmaf(g[e], g[e], gg);  // g = 0 past the end
+      }
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         a[e] = fma(dec, a[e], a[e]);
@@ -252,12 +265,27 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
       for (int k = 0; k < NI; ++k) ix1[k] = ix2[k];
     }
   }
+  if constexpr (RLX) {
+    gg = group_sum<16>(gg);
+    if (it.len > 0) {
+      const double own = pow(rho, (double)it.len);
+      const double after = pow(rho, (double)(row_ptr[it.row + 1] - (it.start + it.len)));
+      float* dst = incr + (int64_t)it.slot * (J + 1);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int j = l + 16 * e;
+        if (j < J) dst[j] = (float)(after * (a[e] - own * (double)Am[(int64_t)it.row * J + j]));
+      }
+      if (l == 0) dst[J] = gg;
+    }
+    return;
+  }
   if (it.len > 0) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = l + 16 * e;
       if (j < J) {
-        if (it.kind == ITEM_LIGHT)
+        if (it.kind == ITEM_LIGHT || hvec == nullptr)
           Am[(int64_t)it.row * J + j] = (float)a[e];
         else
           hvec[(int64_t)it.slot * J + j] = (float)a[e];
@@ -559,6 +587,67 @@ __global__ __launch_bounds__(256) void k_combine_final(const CItem* __restrict__
   }
 }
 
+// FT_RELAXED merge of a long row's chunk increments, in two fixed levels so
+// that rows of many thousand chunks spread over many workgroups and the sums
+// do not depend on timing.  Both levels sum `count` consecutive records of
+// J + 1 values (the increment, then sum ||g||^2) in FP64: thread (sub, j)
+// adds records sub, sub + S, sub + 2 S, ... (S = 256 / J; a wavefront reads
+// 64 / J consecutive records, one contiguous run), then the S partial sums
+// are added in a fixed tree order in LDS.
+template <int J, class In>
+__device__ __forceinline__ void sum_records(const In* __restrict__ base, int count, double (&ssum)[256 / J][J + 1]) {
+  constexpr int S = 256 / J;
+  const int t = threadIdx.x, j = t % J, sub = t / J;
+  double s = 0.0, G = 0.0;
+#pragma unroll 4
+  for (int k = sub; k < count; k += S) {
+    s += (double)base[(int64_t)k * (J + 1) + j];
+    if (j == 0) G += (double)base[(int64_t)k * (J + 1) + J];
+  }
+  ssum[sub][j] = s;
+  if (j == 0) ssum[sub][J] = G;
+  __syncthreads();
+  for (int stride = S / 2; stride >= 1; stride /= 2) {
+    if (sub < stride) {
+      ssum[sub][j] += ssum[sub + stride][j];
+      if (j == 0) ssum[sub][J] += ssum[sub + stride][J];
+    }
+    __syncthreads();
+  }
+}
+
+// Level 1: one workgroup per group of at most kRelaxGroup consecutive chunks
+// of one row; writes the group's FP64 record.
+template <int J>
+__global__ __launch_bounds__(256) void k_relaxed_group(const CItem* __restrict__ items, const float* __restrict__ incr,
+                                                       double* __restrict__ part) {
+  __shared__ double ssum[256 / J][J + 1];
+  const CItem it = items[blockIdx.x];
+  sum_records<J>(incr + it.in_off * (J + 1), it.count, ssum);
+  const int t = threadIdx.x;
+  if (t <= J) part[it.out_off * (J + 1) + t] = ssum[0][t];
+}
+
+// Level 2: one workgroup per long row, over its groups' records.  a_H (the
+// row after its head) is in A(m); the row becomes
+//     a_H + omega ((rho^(L - head) - 1) a_H + sum),
+//     omega = min(1, 1 / (lr sum ||g||^2)).
+template <int J>
+__global__ __launch_bounds__(256) void k_relaxed_merge(const CItem* __restrict__ items, const double* __restrict__ part,
+                                                       float* __restrict__ Am, double lr, double rho) {
+  __shared__ double ssum[256 / J][J + 1];
+  const CItem it = items[blockIdx.x];
+  sum_records<J>(part + it.in_off * (J + 1), it.count, ssum);
+  const int t = threadIdx.x;
+  if (t < J) {
+    const double lg = lr * ssum[0][J];
+    const double omega = lg > 1.0 ? 1.0 / lg : 1.0;
+    const double decay = pow(rho, (double)it.out_off);  // out_off: elements after the head
+    float* a = Am + (int64_t)it.row * J + t;
+    const double aH = (double)*a;
+    *a = (float)(aH + omega * ((decay - 1.0) * aH + ssum[0][t]));
+  }
+}
 
 // One item per 16-lane group: the hardware dispatcher balances the items
 // (measured faster than a grid-stride loop, which also costs registers).
@@ -588,6 +677,33 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr,
     hipLaunchKernelGGL((k_fiber_g<N, J, R, T>), dim3((unsigned)((M.n_fibers + per_block - 1) / per_block)), dim3(256),
                        0, s, D.fib_idx, M.n_fibers, cp, Bm, P->gfib);
   }
+  if constexpr (!NC) {
+    if (P->relaxed) {
+      // short rows and heads (in place), then the chunks from the rows as their heads left them, then the
+      // two merge levels
+      if (M.n_apply > 0) {
+        KTimer tm(P, FT_K_FACTOR_APPLY, s);
+        hipLaunchKernelGGL((k_factor_apply<N, J, R, T, FIB>), dim3(factor_blocks(nullptr, M.n_apply)), dim3(256), 0,
+                           s, D.apply, M.n_apply, D.idx, P->nnz, D.val, cp, Bm, p->A[m], nullptr, flr, c1, D.fid,
+                           P->gfib, nc, P->maps, D.row_ptr, rho);
+      }
+      if (M.n_compose > 0) {
+        KTimer tm(P, FT_K_FACTOR_COMPOSE, s);
+        hipLaunchKernelGGL((k_factor_apply<N, J, R, T, FIB, false, true>), dim3(factor_blocks(nullptr, M.n_compose)),
+                           dim3(256), 0, s, D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm, p->A[m], P->hvec,
+                           flr, c1, D.fid, P->gfib, nc, P->maps, D.row_ptr, rho);
+      }
+      if (M.n_relax > 0) {
+        KTimer tm(P, FT_K_COMBINE, s);
+        double* part = relax_partials(P, m);
+        hipLaunchKernelGGL((k_relaxed_group<J>), dim3((unsigned)M.n_relax_groups), dim3(256), 0, s, D.relax,
+                           P->maps, part);
+        hipLaunchKernelGGL((k_relaxed_merge<J>), dim3((unsigned)M.n_relax), dim3(256), 0, s,
+                           D.relax + M.n_relax_groups, part, p->A[m], lr, rho);
+      }
+      return hipGetLastError();
+    }
+  }
   if (M.n_compose > 0) {
     KTimer tm(P, FT_K_FACTOR_COMPOSE, s);
     hipLaunchKernelGGL((k_factor_compose<N, J, R, T, FIB, NC>),
@@ -600,7 +716,7 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr,
     hipLaunchKernelGGL((k_factor_apply<N, J, R, T, FIB, NC>),
                        dim3(factor_blocks((const void*)k_factor_apply<N, J, R, T, FIB, NC>, M.n_apply)), dim3(256), 0,
                        s, D.apply, M.n_apply, D.idx, P->nnz, D.val, cp, Bm, p->A[m], P->hvec, flr, c1, D.fid, P->gfib,
-                       nc);
+                       nc, P->maps, D.row_ptr, rho);
   }
   for (size_t L = 0; L < M.level_len.size(); ++L) {
     KTimer tm(P, FT_K_COMBINE, s);

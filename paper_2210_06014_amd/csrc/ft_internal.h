@@ -54,6 +54,8 @@ struct ModeHost {
   std::vector<FItem> compose;     // COMPOSE items, padded to multiples of 4
   std::vector<FItem> apply;       // HEAD then LIGHT items, padded to multiples of 4
   std::vector<std::vector<CItem>> levels;
+  std::vector<CItem> relax;       // FT_RELAXED: group items (chunk slots -> group record), then one merge item per
+                                  // heavy row (its group records; out_off = elements after the head)
   std::vector<Seg> segs;
   std::vector<int64_t> seg_ptr;   // I+1: segments of row i are seg_ptr[i]..seg_ptr[i+1]-1
   std::vector<int32_t> fid;       // nnz: fiber of the element at each CSR position
@@ -68,6 +70,7 @@ struct ModeDev {
   FItem* compose = nullptr;
   FItem* apply = nullptr;
   CItem* levels = nullptr;  // all levels back to back
+  CItem* relax = nullptr;
   Seg* segs = nullptr;
   int64_t* seg_ptr = nullptr;
   int32_t* fid = nullptr;
@@ -85,6 +88,8 @@ struct ModeMeta {
   std::vector<int64_t> level_ncomp;  // folds at the head of each level (final items follow)
   int64_t n_level_out0 = 0;        // outputs of level 0 (ping-pong buffer size)
   int64_t n_segs = 0;
+  int64_t n_relax_groups = 0;  // FT_RELAXED level-1 items
+  int64_t n_relax = 0;         // FT_RELAXED level-2 items (heavy rows)
   int64_t n_fibers = 0;
   bool use_fiber = false;
   ft_mode_info info{};
@@ -103,6 +108,7 @@ struct ft_plan {
   int64_t nnz = 0;
   int chunk = 512, head = 1024, fanin = 16;
   bool no_c_cache = false;  // FT_NO_C_CACHE
+  bool relaxed = false;     // FT_RELAXED
   std::vector<ft::ModeMeta> meta;
   std::vector<ft::ModeHost> host;
   std::vector<ft::ModeDev> dev;
@@ -131,6 +137,11 @@ ft_status fail(ft_status s, const std::string& msg);
 // kernel launchers (ft_refresh.hip, ft_factor.hip, ft_segment.hip); return hipSuccess or the launch error
 constexpr int kPartials = 2048;  // max workgroups of the reduction kernels
 constexpr int kSegLen = 512;     // max elements per segment
+constexpr int kRelaxGroup = 256; // chunks per level-1 group of the relaxed merge
+
+// FT_RELAXED scratch in P->maps: J + 1 floats per chunk slot, then (8-byte
+// aligned) J + 1 doubles per level-1 group
+inline int64_t relax_incr_floats(int64_t n_maps, int J) { return (n_maps * (J + 1) + 1) / 2 * 2; }
 
 // Brackets one kernel launch with events when timing is enabled on the plan.
 struct KTimer {
@@ -150,6 +161,10 @@ struct KTimer {
       (void)hipEventDestroy(a);
   }
 };
+
+inline double* relax_partials(const ft_plan* P, int m) {
+  return reinterpret_cast<double*>(P->maps + relax_incr_floats(P->meta[m].n_maps, P->J));
+}
 
 hipError_t launch_refresh(const ft_plan* P, int n, const ft_params* p, hipStream_t s);
 hipError_t launch_factor(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s);

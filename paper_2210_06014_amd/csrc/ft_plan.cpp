@@ -247,6 +247,29 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
     ++level;
   }
 
+  // relaxed merge items: a heavy row's chunk increments are slots
+  // heavy_base .. heavy_base + K - 1, in row order.  Level 1 sums groups of
+  // kRelaxGroup consecutive slots of one row into group records; level 2 sums
+  // a row's group records (consecutive) and updates the row.  Larger rows first.
+  if (P->relaxed) {
+    std::vector<CItem> merges;
+    int64_t n_groups = 0;
+    for (int64_t h = 0; h < n_heavy; ++h) {
+      const int64_t i = heavy_rows[h], L = H.row_ptr[i + 1] - H.row_ptr[i], K = heavy_nmaps[h];
+      const int64_t ng = (K + kRelaxGroup - 1) / kRelaxGroup;
+      for (int64_t g = 0; g < ng; ++g)
+        H.relax.push_back(CItem{heavy_base[h] + g * kRelaxGroup, n_groups + g,
+                                (int32_t)std::min<int64_t>(kRelaxGroup, K - g * kRelaxGroup), (int32_t)i,
+                                (int32_t)h, 0});
+      merges.push_back(CItem{n_groups, L - hl, (int32_t)ng, (int32_t)i, (int32_t)h, 0});
+      n_groups += ng;
+    }
+    std::stable_sort(H.relax.begin(), H.relax.end(), [](const CItem& x, const CItem& y) { return x.count > y.count; });
+    std::stable_sort(merges.begin(), merges.end(), [](const CItem& x, const CItem& y) { return x.count > y.count; });
+    M.n_relax_groups = n_groups;
+    H.relax.insert(H.relax.end(), merges.begin(), merges.end());
+  }
+
   // segments for the core, loss and gradient passes
   H.seg_ptr.assign((size_t)I + 1, 0);
   for (int64_t i = 0; i < I; ++i) {
@@ -273,6 +296,7 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   M.n_maps = n_maps;
   M.n_level_out0 = out0;
   M.n_segs = (int64_t)H.segs.size();
+  M.n_relax = (int64_t)H.relax.size() - M.n_relax_groups;
   int64_t off = 0;
   for (auto& L : H.levels) {
     M.level_off.push_back(off);
@@ -315,6 +339,8 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
     return fail(FT_ERR_ARG, "bad chunk, head or fanin");
   if ((d->flags & FT_NO_C_CACHE) && !(d->order == 3 && d->J[0] == 16 && d->R == 16))
     return fail(FT_ERR_UNSUPPORTED, "FT_NO_C_CACHE is built for order 3 with J = R = 16 only");
+  if ((d->flags & FT_RELAXED) && (d->flags & FT_NO_C_CACHE))
+    return fail(FT_ERR_UNSUPPORTED, "FT_RELAXED is not built with FT_NO_C_CACHE");
   if ((d->flags & FT_WITH_PERM) && d->nnz > 0x7FFFFFFF) return fail(FT_ERR_SHAPE, "FT_WITH_PERM needs nnz < 2^31");
   const int N = d->order;
   const int64_t nnz = d->nnz;
@@ -350,6 +376,7 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
   P->chunk = d->chunk ? d->chunk : 512;
   P->head = d->head ? d->head : 2 * P->chunk;
   P->no_c_cache = (d->flags & FT_NO_C_CACHE) != 0;
+  P->relaxed = (d->flags & FT_RELAXED) != 0;
   P->fanin = std::min(d->fanin ? d->fanin : max_fanin(d->J[0]), max_fanin(d->J[0]));
   try {
     P->meta.resize(N);
@@ -394,6 +421,7 @@ void free_dev(ft_plan* P) {
     (void)hipFree(D.row_ptr); (void)hipFree(D.idx); (void)hipFree(D.val); (void)hipFree(D.perm);
     (void)hipFree(D.compose); (void)hipFree(D.fid); (void)hipFree(D.fib_idx);
     (void)hipFree(D.apply); (void)hipFree(D.levels); (void)hipFree(D.segs); (void)hipFree(D.seg_ptr);
+    (void)hipFree(D.relax);
     D = ModeDev{};
   }
   (void)hipFree(P->maps); (void)hipFree(P->map_scale); (void)hipFree(P->hvec); (void)hipFree(P->partials);
@@ -432,6 +460,7 @@ extern "C" ft_status ft_plan_upload(ft_plan* P, void* stream) {
       for (auto& L : H.levels) all.insert(all.end(), L.begin(), L.end());
       e = upload(&D.levels, all, bytes);
     }
+    if (e == hipSuccess && P->relaxed) e = upload(&D.relax, H.relax, bytes);
     if (e == hipSuccess) e = upload(&D.segs, H.segs, bytes);
     if (e == hipSuccess) e = upload(&D.seg_ptr, H.seg_ptr, bytes);
     if (e == hipSuccess && M.use_fiber) e = upload(&D.fid, H.fid, bytes);
@@ -442,7 +471,10 @@ extern "C" ft_status ft_plan_upload(ft_plan* P, void* stream) {
     max_segs = std::max(max_segs, M.n_segs);
   }
   const int J = P->J, R = P->R;
-  if (e == hipSuccess) e = alloc(&P->maps, (size_t)max_slots * (J * J + J), bytes);
+  int64_t map_floats = max_slots * (J * J + J);
+  for (int m = 0; m < P->N && P->relaxed; ++m)
+    map_floats = std::max(map_floats, relax_incr_floats(P->meta[m].n_maps, J) + 2 * P->meta[m].n_relax_groups * (J + 1));
+  if (e == hipSuccess) e = alloc(&P->maps, (size_t)map_floats, bytes);
   if (e == hipSuccess) e = alloc(&P->map_scale, (size_t)max_slots, bytes);
   if (e == hipSuccess) e = alloc(&P->hvec, (size_t)max_heavy * J, bytes);
   if (e == hipSuccess) e = alloc(&P->partials, (size_t)(kPartials + kPartials / 32 + 1) * J * R, bytes);

@@ -137,3 +137,18 @@ def test_no_c_cache_flag():
         with pytest.raises(ft.FtError) as e:
             ft.Plan(d, J, R, cc, np.ones(500, dtype=np.float32), keep_host=True, upload=False, c_cache=False)
         assert e.value.status == 4
+
+
+def test_relaxed_flag():
+    """FT_RELAXED keeps the plan's work lists as they are; it is refused with FT_NO_C_CACHE."""
+    dims = [40, 30, 20]
+    c, _ = synth.coords(dims, 6000, 1.2, seed=8)
+    v = np.ones(c.shape[1], dtype=np.float32)
+    exact = _plan(dims, 16, 16, c, v, chunk=16, head=40)
+    relaxed = _plan(dims, 16, 16, c, v, chunk=16, head=40, relaxed=True)
+    for m in range(3):
+        assert exact.mode_info(m) == relaxed.mode_info(m)
+        assert relaxed.mode_info(m)["heavy_rows"] > 0
+    with pytest.raises(ft.FtError) as e:
+        _plan(dims, 16, 16, c, v, relaxed=True, c_cache=False)
+    assert e.value.status == 4
