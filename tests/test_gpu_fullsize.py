@@ -75,3 +75,35 @@ def test_factor_passes_sampled_rows(netflix):
             ok, err, bound = delta_ok(got[k], want[k], before[k])
             assert ok, (m, int(i), int(counts[i]), err, bound)
         ft.refresh(plan, prm, m)
+
+
+def test_relaxed_factor_passes_sampled_rows(netflix):
+    """FT_RELAXED at full size (the plan of `bench.py --relaxed`): sampled rows against the oracle's
+    relaxed module run on exactly their elements, from the same starting state."""
+    import torch
+
+    import paper_2210_06014_amd as ft
+
+    w, c, v, A, B, _, _ = netflix
+    J, R = w.J[0], w.R
+    plan = ft.Plan(w.dims, J, R, c, v, relaxed=True)
+    prm = ft.Params(A, B)
+    ft.refresh(plan, prm)
+    for m in range(3):
+        A_now = [to_np(a) for a in prm.A]
+        B_now = [to_np(b) for b in prm.B]
+        ft.factor_pass(plan, prm, m, w.lr, w.lam)
+        torch.cuda.synchronize()
+        counts = np.bincount(c[m], minlength=w.dims[m])
+        rows = _sample_rows(counts)
+        sel = np.isin(c[m], rows)
+        print(f"[fullsize relaxed] mode {m}: rows {rows.tolist()} lengths {counts[rows].tolist()}", flush=True)
+        orc = oracle.Model(w.dims, w.J, R, np.ascontiguousarray(c[:, sel]), v[sel].astype(np.float64), A_now, B_now)
+        orc.factor_pass_relaxed(m, w.lr, w.lam, 1024, 512)
+        got = to_np(prm.A[m])[rows]
+        want = orc.A[m][rows]
+        before = A_now[m][rows]
+        for k, i in enumerate(rows):
+            ok, err, bound = delta_ok(got[k], want[k], before[k])
+            assert ok, (m, int(i), int(counts[i]), err, bound)
+        ft.refresh(plan, prm, m)
