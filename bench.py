@@ -238,8 +238,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(
-            json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md "
-                        "and not implemented", "n_gpus": args.gpus}),
+            json.dumps({"error": "the library runs on one GPU only; sharding across GPUs is not implemented",
+                        "n_gpus": args.gpus}),
             flush=True,
         )
         sys.exit(2)

@@ -15,7 +15,7 @@
  * Every array is row-major FP64.  Coordinates are int32, structure of arrays:
  * the mode-n index of element x is coords[n * stride + x].
  *
- * Readings where the paper is silent or inconsistent (listed in the design doc):
+ * Readings where the paper is silent or inconsistent:
  *  - update direction: the gradients of Eq. (10) and Eq. (11) are followed,
  *    a <- a - lr * (-(x - xhat) g + lam a); the pseudo-code of the GPU
  *    algorithms prints the opposite sign in places;
