@@ -208,7 +208,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="netflix")
     ap.add_argument("--nnz", type=int, default=None, help="override the element count (smaller test runs)")
-    ap.add_argument("--cpu-sample", type=int, default=3_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--chunk", type=int, default=0, help="elements per chunk map of a long row (0: library default)")
