@@ -188,7 +188,12 @@ static double sgd_step(int N, int m, int J, int R, const double* Bm, const doubl
  *
  * A row's elements are taken in the order i_m, i_{m+1}, ..., i_{m-1} (the
  * per-row order of the fiber traversal).  A row of at most `head` elements is
- * updated serially, exactly as in orc_factor_pass.  A longer row:
+ * updated serially, exactly as in orc_factor_pass.  A longer row of L
+ * elements is first dealt in stride order: with Q = ceil(L / head), its
+ * positions 0, Q, 2Q, ..., then 1, 1 + Q, ..., then 2, ... (a worker that
+ * takes a piece of a long row sees a sample of the whole row, not a narrow
+ * slice of the sorted order; with contiguous pieces the pass diverged on a
+ * learning workload once the head reached 4096 elements).  Then, in that order:
  *   - its first `head` elements update the row serially, from a0 to a_H;
  *   - the rest is cut into chunks of `chunk` elements; every chunk k runs its
  *     steps serially from a_H (all chunks read the row as the head left it),
@@ -223,8 +228,9 @@ int orc_factor_pass_relaxed(int N, const int64_t* dims, const int* Jv, int R, do
   double* g = (double*)malloc(sizeof(double) * J);
   double* b = (double*)malloc(sizeof(double) * J);
   double* S = (double*)malloc(sizeof(double) * J);
-  if (!ord || !w || !g || !b || !S) {
-    free(ord); free(w); free(g); free(b); free(S);
+  int64_t* dealt = (int64_t*)malloc(sizeof(int64_t) * (nnz > 0 ? nnz : 1));
+  if (!ord || !w || !g || !b || !S || !dealt) {
+    free(ord); free(w); free(g); free(b); free(S); free(dealt);
     return ORC_ERR_NOMEM;
   }
   for (int64_t x = 0; x < nnz; ++x) ord[x] = x;
@@ -241,6 +247,12 @@ int orc_factor_pass_relaxed(int N, const int64_t* dims, const int* Jv, int R, do
     int64_t L = q - p;
     double* a = Am + (int64_t)row * J;
     int64_t hl = L <= head ? L : head;
+    if (L > head && head > 0) {
+      int64_t Q = (L + head - 1) / head, o = 0;
+      for (int64_t r = 0; r < Q; ++r)
+        for (int64_t t = r; t < L; t += Q) dealt[o++] = ord[p + t];
+      for (int64_t t = 0; t < L; ++t) ord[p + t] = dealt[t];
+    }
     for (int64_t t = 0; t < hl; ++t) sgd_step(N, m, J, R, Bm, C, coords, vals, nnz, ord[p + t], lr, lam, a, w, g);
     if (L > head) {
       /* a holds a_H from here on */
@@ -259,7 +271,7 @@ int orc_factor_pass_relaxed(int N, const int64_t* dims, const int* Jv, int R, do
     }
     p = q;
   }
-  free(ord); free(w); free(g); free(b); free(S);
+  free(ord); free(w); free(g); free(b); free(S); free(dealt);
   return ORC_OK;
 }
 

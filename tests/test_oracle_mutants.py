@@ -25,6 +25,8 @@ MUTANTS = [
     ("loss: sum of residuals instead of squares", "    sse += e * e;", "    sse += e;"),
     ("relaxed: chunk weight without the later decay", "decay_after = pow(rho, (double)(L - c1))", "decay_after = 1.0"),
     ("relaxed: guard off", "double omega = lr * G > 1.0 ? 1.0 / (lr * G) : 1.0;", "double omega = 1.0;"),
+    ("relaxed: long rows not dealt in stride order", "    if (L > head && head > 0) {\n      int64_t Q",
+     "    if (0) {\n      int64_t Q"),
     ("relaxed: guard on the increments only",
      "a[j] = a[j] + omega * ((decay_rest - 1.0) * a[j] + S[j]);", "a[j] = decay_rest * a[j] + omega * S[j];"),
 ]

@@ -168,3 +168,35 @@ def test_decay_only_closed_form():
     L = np.bincount(c[0], minlength=dims[0])
     want = A[0] * (1 - lr * lam) ** L[:, None]
     np.testing.assert_allclose(m.A[0], want, rtol=1e-13)
+
+
+def test_long_rows_are_dealt_in_stride_order():
+    """A row of L = 12 elements with head = chunk = 4 is dealt with stride Q = ceil(L / head) = 3: the head
+    is the sorted positions 0, 3, 6, 9 and the two chunks are 1, 4, 7, 10 and 2, 5, 8, 11.  Each piece is run
+    here by the serial module (pinned on its own) on exactly its elements, and merged as defined."""
+    rng = np.random.default_rng(41)
+    dims, J, R = (1, 4, 3), [3, 3, 3], 4
+    A, B = _rng_params(rng, dims, J, R, 0.6)
+    grid = np.stack(np.meshgrid(np.arange(1), np.arange(4), np.arange(3), indexing="ij")).reshape(3, -1)
+    coords = grid.astype(np.int32)  # already in the row's sorted order (i_1, i_2)
+    vals = rng.integers(1, 6, size=coords.shape[1]).astype(np.float64)
+    lr, lam = 0.05, 0.1
+    rho = 1.0 - lr * lam
+
+    def serial(pos, start):
+        m = oracle.Model(dims, J, R, coords[:, pos], vals[pos], [start[None, :], A[1], A[2]], B)
+        m.factor_pass(0, lr, lam)
+        return m.A[0][0]
+
+    a_head = serial([0, 3, 6, 9], A[0][0])
+    b1 = serial([1, 4, 7, 10], a_head)
+    b2 = serial([2, 5, 8, 11], a_head)
+    S = rho ** 4 * (b1 - rho ** 4 * a_head) + (b2 - rho ** 4 * a_head)
+    C1, C2 = A[1] @ B[1], A[2] @ B[2]
+    g = (C1[coords[1]] * C2[coords[2]]) @ B[0].T
+    G = np.sum(g[[1, 4, 7, 10, 2, 5, 8, 11]] ** 2)
+    omega = min(1.0, 1.0 / (lr * G))
+    want = a_head + omega * ((rho ** 8 - 1.0) * a_head + S)
+    m = oracle.Model(dims, J, R, coords, vals, A, B)
+    m.factor_pass_relaxed(0, lr, lam, head=4, chunk=4)
+    np.testing.assert_allclose(m.A[0][0], want, rtol=1e-12)
