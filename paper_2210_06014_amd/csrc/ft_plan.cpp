@@ -166,6 +166,41 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
     return fail(FT_ERR_NOMEM, "host allocation failed while sorting mode " + std::to_string(m));
   }
 
+  // FT_RELAXED: a row longer than the head is dealt in stride order
+  // (Q = ceil(L / head): positions 0, Q, 2Q, ..., then 1, 1 + Q, ...) so that
+  // its head and each chunk hold a sample of the whole row rather than a
+  // narrow slice of the sorted order.  Only the factor passes depend on the
+  // order within a row; the segment sums of the other passes do not.
+  if (P->relaxed && P->head > 0) {
+    const int64_t hl0 = P->head;
+    int64_t maxL = 0;
+    for (int64_t i = 0; i < I; ++i) maxL = std::max(maxL, H.row_ptr[i + 1] - H.row_ptr[i]);
+    try {
+      std::vector<int64_t> src((size_t)std::max<int64_t>(maxL, 1));
+      std::vector<int32_t> t32((size_t)std::max<int64_t>(maxL, 1));
+      std::vector<int64_t> t64((size_t)std::max<int64_t>(maxL, 1));
+      std::vector<float> tf((size_t)std::max<int64_t>(maxL, 1));
+      auto deal = [&](auto* base, auto& tmp, int64_t s, int64_t L) {
+        for (int64_t t = 0; t < L; ++t) tmp[t] = base[s + src[t]];
+        for (int64_t t = 0; t < L; ++t) base[s + t] = tmp[t];
+      };
+      for (int64_t i = 0; i < I; ++i) {
+        const int64_t s = H.row_ptr[i], L = H.row_ptr[i + 1] - s;
+        if (L <= hl0) continue;
+        const int64_t Q = (L + hl0 - 1) / hl0;
+        int64_t o = 0;
+        for (int64_t r = 0; r < Q; ++r)
+          for (int64_t t = r; t < L; t += Q) src[o++] = t;
+        for (int k = 0; k < N - 1; ++k) deal(H.idx.data() + (int64_t)k * nnz, t32, s, L);
+        deal(H.val.data(), tf, s, L);
+        deal(H.perm.data(), t64, s, L);
+        if (!H.fid.empty()) deal(H.fid.data(), t32, s, L);
+      }
+    } catch (const std::bad_alloc&) {
+      return fail(FT_ERR_NOMEM, "host allocation failed while dealing mode " + std::to_string(m));
+    }
+  }
+
   // factor work lists: a row of at most `head` elements is one serial item;
   // a longer row is a head item (its first `head` elements, updated in
   // place) followed by chunk items whose maps the combine applies in order
