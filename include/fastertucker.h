@@ -61,18 +61,18 @@ typedef enum {
                                storage only (FT_ERR_UNSUPPORTED otherwise); loss, predict and gradient calls
                                still read C, which the refreshes keep current */
 #define FT_RELAXED 16       /* relaxed factor passes, modelled on the unordered concurrent row updates of the
-                               GPU factor algorithm (Algorithm 4).  A row longer than `head` has its head
-                               updated in place (a_H); its chunks then all start from a_H, as concurrent
-                               workers reading the row would; chunk k's increment beyond the decay of a_H,
-                               d_k, is weighted by rho^T_k (rho = 1 - lr lam, T_k the row's elements after
-                               the chunk), and the row becomes a_H + omega ((rho^(L - head) - 1) a_H +
-                               sum_k rho^T_k d_k) with omega = min(1, 1 / (lr sum ||g||^2)) over the chunked
-                               elements, which keeps the merged step from overshooting.  Not the serial
-                               result of Algorithm 2 (it agrees to second order in lr); deterministic.  Rows
-                               of at most `head` elements are updated exactly as without the flag.  On a
-                               planted low-rank test tensor trained with lr = lam = 1e-2 it converged at the
-                               default head and diverged with heads of 4096 and 16384.  Not with
-                               FT_NO_C_CACHE (FT_ERR_UNSUPPORTED) */
+                               GPU factor algorithm (Algorithm 4).  The plan deals each row longer than
+                               `head` in stride order (Q = ceil(L / head): positions 0, Q, 2Q, ..., then
+                               1, 1 + Q, ...), so that its head and its chunks each hold a sample of the
+                               whole row.  The head is updated in place (a_H); the chunks then all start
+                               from a_H, as concurrent workers reading the row would; chunk k's increment
+                               beyond the decay of a_H, d_k, is weighted by rho^T_k (rho = 1 - lr lam, T_k
+                               the row's elements after the chunk), and the row becomes a_H + omega
+                               ((rho^(L - head) - 1) a_H + sum_k rho^T_k d_k) with omega = min(1, 1 / (lr
+                               sum ||g||^2)) over the chunked elements, which keeps the merged step from
+                               overshooting.  Not the serial result of Algorithm 2 (it agrees to second
+                               order in lr); deterministic.  Rows of at most `head` elements are updated
+                               exactly as without the flag.  Not with FT_NO_C_CACHE (FT_ERR_UNSUPPORTED) */
 
 /* Shape of the problem and of the plan. */
 typedef struct {
@@ -162,6 +162,8 @@ ft_status ft_plan_device_bytes(const ft_plan* plan, size_t* bytes);
  *   row_ptr int64[I_m + 1]; idx int32[(N-1) * nnz] where column k holds the
  *   indices of mode (m + 1 + k) mod N; vals float[nnz]; perm int64[nnz]
  *   maps a CSR position to the element's input position.  Any may be NULL.
+ *   Rows are sorted by (i_m, i_{m+1}, ..., i_{m-1}); with FT_RELAXED the rows
+ *   longer than the head hold their elements in the dealt (stride) order.
  */
 ft_status ft_plan_host_csr(const ft_plan* plan, int32_t mode, int64_t* row_ptr, int32_t* idx, float* vals,
                            int64_t* perm);
