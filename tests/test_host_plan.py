@@ -152,3 +152,31 @@ def test_relaxed_flag():
     with pytest.raises(ft.FtError) as e:
         _plan(dims, 16, 16, c, v, relaxed=True, c_cache=False)
     assert e.value.status == 4
+
+
+def test_relaxed_plan_deals_long_rows():
+    """FT_RELAXED: a row longer than the head holds its sorted elements in stride order (Q = ceil(L / head):
+    sorted positions 0, Q, 2Q, ..., then 1, 1 + Q, ...) in every per-element array; other rows keep the
+    sorted order."""
+    dims = [40, 30, 20]
+    c, _ = synth.coords(dims, 6000, 1.2, seed=8)
+    v = synth.values(c.shape[1], "int1to5", seed=8)
+    head = 40
+    exact = _plan(dims, 8, 8, c, v, chunk=16, head=head)
+    relaxed = _plan(dims, 8, 8, c, v, chunk=16, head=head, relaxed=True)
+    dealt_rows = 0
+    for m in range(3):
+        rp, idx, vals, perm = exact.host_csr(m)
+        rp2, idx2, vals2, perm2 = relaxed.host_csr(m)
+        np.testing.assert_array_equal(rp, rp2)
+        for i in range(dims[m]):
+            s, L = int(rp[i]), int(rp[i + 1] - rp[i])
+            order = np.arange(L)
+            if L > head:
+                Q = -(-L // head)
+                order = np.concatenate([np.arange(r, L, Q) for r in range(Q)])
+                dealt_rows += 1
+            np.testing.assert_array_equal(perm2[s:s + L], perm[s:s + L][order])
+            np.testing.assert_array_equal(vals2[s:s + L], vals[s:s + L][order])
+            np.testing.assert_array_equal(idx2[:, s:s + L], idx[:, s:s + L][:, order])
+    assert dealt_rows > 0
