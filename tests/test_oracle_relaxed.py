@@ -4,9 +4,10 @@ merged under a step guard).
 The relaxed module is a reading of the unordered row updates of Algorithm 4,
 not a formula the paper prints, so it is pinned by what its definition forces:
 it is the serial pass of Algorithm 2 when no row is cut into chunks, it agrees
-with the serial pass to second order in the learning rate, and on a row whose
+with the serial pass to second order in the learning rate, on a row whose
 elements all share one g it follows the geometric closed form of SGD on a
-single linear equation, guard included.
+single linear equation, guard included, and its head and chunks are the
+residue classes of the stride deal, each equal to the serial pass over them.
 """
 import numpy as np
 import pytest
