@@ -50,3 +50,27 @@ def test_iteration_high_order(order, shape):
     got = to_np(ft.loss(plan, prm, 1e-2, 1e-2))
     ref = np.asarray(orc.loss(1e-2, 1e-2))
     np.testing.assert_allclose(got, ref, rtol=1e-4)
+
+
+@pytest.mark.parametrize("order", ORDERS)
+def test_relaxed_factor_passes_high_order(order):
+    """FT_RELAXED at orders 5..10 (J = R = 32): every mode's relaxed factor pass against the oracle's
+    relaxed module, on the Zipf-rows tensor (long rows dealt, heads and chunks, two merge levels)."""
+    import paper_2210_06014_amd as ft
+
+    J = R = 32
+    dims, nnz, zipf, kw = _shapes(order)["zipf_rows"]
+    print(f"\n[relaxed order {order}] dims={dims} nnz={nnz}", flush=True)
+    c, v, A, B = make_problem(dims, nnz, zipf, J, R, seed=60 + order, sigma=0.35)
+    plan, prm = gpu_setup(dims, J, R, c, v, A, B, relaxed=True, **kw)
+    assert plan.mode_info(0)["heavy_rows"] > 0
+    orc = oracle_model(dims, J, R, c, v, A, B)
+    chunk = kw["chunk"]
+    for m in range(order):
+        before = orc.A[m].copy()
+        ft.factor_pass(plan, prm, m, 1e-3, 1e-2)
+        orc.factor_pass_relaxed(m, 1e-3, 1e-2, 2 * chunk, chunk)
+        ok, err, bound = delta_ok(to_np(prm.A[m]), orc.A[m], before)
+        assert ok, (order, m, err, bound)
+        ft.refresh(plan, prm, m)
+        orc.refresh(m)
