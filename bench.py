@@ -265,7 +265,7 @@ def main():
     t = time.time()
     plan = ft.Plan(w.dims, J, R, c, v, chunk=args.chunk, head=args.head, fiber_share=not args.no_fiber_share,
                    c_cache=not args.no_c_cache, relaxed=args.relaxed)
-    log(f"plan built and uploaded in {time.time() - t:.1f} s ({plan.device_bytes() / 2**30:.2f} GiB on device)")
+    log(f"plan built and uploaded in {time.time() - t:.1f} s ({plan.device_bytes / 2**30:.2f} GiB on device)")
     prm = ft.Params(A, B, storage=args.storage)
     ft.refresh(plan, prm)
     rmse0 = float(ft.loss(plan, prm)[1].item())

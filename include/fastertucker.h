@@ -12,17 +12,25 @@
  * over Omega, Algorithm 5), each followed by a refresh of C(m).
  *
  * Conventions shared by every entry point:
+ *  - The library allocates no device memory.  The caller owns every device
+ *    buffer: the plan's arrays live in a workspace the caller hands to
+ *    ft_plan_upload (size from ft_plan_query), and each parameter set brings
+ *    its own scratch buffer (ft_params.scratch, size from ft_plan_query).
+ *    Both must be 256-byte aligned (torch allocations are).
  *  - Matrices are dense row-major FP32 in device memory owned by the caller
- *    (A(n): I_n x J, B(n): J x R, C(n): I_n x R).  All J_n must be equal.
+ *    (A(n): I_n x J, B(n): J x R, C(n): I_n x R).  Eq. (1) allows a J_n per
+ *    mode; the kernels are compiled for one J shared by all modes, so every
+ *    J_n must be equal (FT_ERR_UNSUPPORTED otherwise).
  *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
  *    Work is enqueued on it and the call returns without synchronising,
- *    except where stated.  A plan may be shared by parameter sets; one plan
- *    or parameter set must not be used on two streams at once (the plan owns
- *    scratch buffers that every call reuses).
+ *    except where stated.  A plan is immutable once uploaded and may be
+ *    shared by any number of parameter sets, on any streams; a parameter set
+ *    (its scratch) must not be used on two streams at once.
  *  - Return value: FT_OK, or an error code with a message available from
- *    ft_last_error() (thread-local).  Argument, shape and index errors are
- *    detected on the host before anything is enqueued; FT_ERR_HIP reports a
- *    failed HIP call or kernel launch.  No exception crosses the ABI.
+ *    ft_last_error() (thread-local).  Argument, shape, index and workspace
+ *    errors are detected on the host before anything is enqueued;
+ *    FT_ERR_HIP reports a failed HIP call or kernel launch.  No exception
+ *    crosses the ABI.
  *  - Floating point: FP32 arithmetic with FMA contraction, IEEE round to
  *    nearest even.  Sums over elements run in a fixed order, so results are
  *    bitwise repeatable for a given plan and input.  FP64 is used on the GPU
@@ -46,7 +54,8 @@ typedef enum {
   FT_ERR_UNSUPPORTED = 4, /* (order, J, R) combination not compiled in */
   FT_ERR_STATE = 5,       /* plan not uploaded, host copy not kept, ... */
   FT_ERR_NOMEM = 6,       /* host allocation failed */
-  FT_ERR_HIP = 7          /* a HIP call failed (device memory, launch) */
+  FT_ERR_HIP = 7,         /* a HIP call failed (copy, launch) */
+  FT_ERR_WORKSPACE = 8    /* a workspace or scratch buffer is missing, too small or misaligned */
 } ft_status;
 
 #define FT_MAX_ORDER 10
@@ -77,7 +86,7 @@ typedef enum {
 /* Shape of the problem and of the plan. */
 typedef struct {
   int32_t order;                /* N, 2..FT_MAX_ORDER */
-  int64_t dims[FT_MAX_ORDER];   /* I_n, 1..2^31-1 */
+  int64_t dims[FT_MAX_ORDER];   /* I_n >= 1 with I_n * R * 4 < 2^31 (C rows are gathered by 32-bit byte offsets) */
   int32_t J[FT_MAX_ORDER];      /* factor rank per mode; must all be equal */
   int32_t R;                    /* core rank */
   int64_t nnz;                  /* |Omega|, 0..2^32-1 */
@@ -113,6 +122,9 @@ typedef struct {
   void* B16[FT_MAX_ORDER];
   void* C16[FT_MAX_ORDER];
   int32_t storage;
+  void* scratch;        /* device buffer of at least scratch_bytes (ft_plan_query) for the plans it is used with:
+                           chunk maps, partial sums and shared g that the passes write between launches */
+  size_t scratch_bytes; /* its size */
 } ft_params;
 
 /* Host-side statistics of one mode of a plan (for diagnostics and tests). */
@@ -145,17 +157,33 @@ typedef struct ft_plan ft_plan;
  */
 ft_status ft_plan_create(ft_plan** out, const ft_desc* desc, const int32_t* coords, const float* vals);
 
-/* ft_plan_upload -- allocates the plan's device memory and copies it
- * (synchronous).  Frees the host copy unless FT_KEEP_HOST was given. */
-ft_status ft_plan_upload(ft_plan* plan, void* stream);
+/*
+ * ft_plan_query -- device bytes the plan needs (valid from ft_plan_create on):
+ *   device_bytes:  its sorted arrays and work lists, the workspace of
+ *                  ft_plan_upload;
+ *   scratch_bytes: the scratch each parameter set used with the plan must
+ *                  bring (ft_params.scratch).
+ * The sizes follow from the sorted tensor (rows, long-row chunks, segments,
+ * fibers), so they are known only once the host plan exists.  Either
+ * output may be NULL.
+ */
+ft_status ft_plan_query(const ft_plan* plan, size_t* device_bytes, size_t* scratch_bytes);
 
-/* Frees host and device memory of the plan (synchronises the device). */
+/*
+ * ft_plan_upload -- copies the plan's arrays into the caller's device buffer
+ * d_workspace (at least device_bytes, 256-byte aligned), with
+ * hipMemcpyAsync on `stream`, and waits for the copies; then frees the host
+ * copy unless FT_KEEP_HOST was given.  The workspace must stay allocated and
+ * unmodified while the plan is used.  With FT_KEEP_HOST the plan can be
+ * uploaded again (to another workspace); otherwise a second upload is
+ * FT_ERR_STATE.  Errors: FT_ERR_ARG, FT_ERR_STATE, FT_ERR_WORKSPACE, FT_ERR_HIP.
+ */
+ft_status ft_plan_upload(ft_plan* plan, void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* Frees the host side of the plan (device memory belongs to the caller). */
 void ft_plan_destroy(ft_plan* plan);
 
 ft_status ft_plan_mode_info(const ft_plan* plan, int32_t mode, ft_mode_info* info);
-
-/* Device bytes held by the plan (valid after upload). */
-ft_status ft_plan_device_bytes(const ft_plan* plan, size_t* bytes);
 
 /*
  * ft_plan_host_csr -- copy of the host CSR of one mode (needs FT_KEEP_HOST).

@@ -23,15 +23,16 @@ STATUS = {
     5: "FT_ERR_STATE",
     6: "FT_ERR_NOMEM",
     7: "FT_ERR_HIP",
+    8: "FT_ERR_WORKSPACE",
 }
 
 # every entry point of include/fastertucker.h
 SYMBOLS = [
     "ft_plan_create",
+    "ft_plan_query",
     "ft_plan_upload",
     "ft_plan_destroy",
     "ft_plan_mode_info",
-    "ft_plan_device_bytes",
     "ft_plan_host_csr",
     "ft_refresh",
     "ft_predict",
@@ -79,6 +80,8 @@ class FtParams(ctypes.Structure):
         ("B16", ctypes.c_void_p * MAX_ORDER),
         ("C16", ctypes.c_void_p * MAX_ORDER),
         ("storage", ctypes.c_int32),
+        ("scratch", ctypes.c_void_p),
+        ("scratch_bytes", ctypes.c_size_t),
     ]
 
 
@@ -124,10 +127,10 @@ def load():
     P = ctypes.POINTER
     sig = {
         "ft_plan_create": ([P(vp), P(FtDesc), vp, vp], i32),
-        "ft_plan_upload": ([vp, vp], i32),
+        "ft_plan_query": ([vp, P(ctypes.c_size_t), P(ctypes.c_size_t)], i32),
+        "ft_plan_upload": ([vp, vp, ctypes.c_size_t, vp], i32),
         "ft_plan_destroy": ([vp], None),
         "ft_plan_mode_info": ([vp, i32, P(FtModeInfo)], i32),
-        "ft_plan_device_bytes": ([vp, P(ctypes.c_size_t)], i32),
         "ft_plan_host_csr": ([vp, i32, vp, vp, vp, vp], i32),
         "ft_refresh": ([vp, P(FtParams), i32, vp], i32),
         "ft_predict": ([vp, P(FtParams), vp, i64, vp, vp], i32),

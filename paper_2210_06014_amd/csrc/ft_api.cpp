@@ -29,6 +29,16 @@ ft_status check_params(const ft_plan* P, const ft_params* p) {
   return FT_OK;
 }
 
+// the parameter set's scratch buffer, for the calls that write scratch
+ft_status check_scratch(const ft_plan* P, const ft_params* p) {
+  if (!p->scratch || p->scratch_bytes < P->scratch_bytes)
+    return fail(FT_ERR_WORKSPACE, "parameter scratch of " + std::to_string(p->scratch ? p->scratch_bytes : 0) +
+                                      " bytes, the plan needs " + std::to_string(P->scratch_bytes));
+  if (reinterpret_cast<uintptr_t>(p->scratch) % kAlign)
+    return fail(FT_ERR_WORKSPACE, "parameter scratch not 256-byte aligned");
+  return FT_OK;
+}
+
 ft_status check_mode(const ft_plan* P, int32_t m) {
   if (m < 0 || m >= P->N) return fail(FT_ERR_ARG, "mode out of range");
   return FT_OK;
@@ -63,6 +73,7 @@ extern "C" const char* ft_status_str(ft_status s) {
     case FT_ERR_STATE: return "FT_ERR_STATE";
     case FT_ERR_NOMEM: return "FT_ERR_NOMEM";
     case FT_ERR_HIP: return "FT_ERR_HIP";
+    case FT_ERR_WORKSPACE: return "FT_ERR_WORKSPACE";
   }
   return "FT_ERR_UNKNOWN";
 }
@@ -97,18 +108,21 @@ extern "C" ft_status ft_factor_pass(const ft_plan* P, const ft_params* p, int32_
                                     void* stream) {
   FT_TRY(check_plan(P));
   FT_TRY(check_params(P, p));
+  FT_TRY(check_scratch(P, p));
   FT_TRY(check_mode(P, mode));
   FT_TRY(check_lr(lr, lam));
-  return hip_status(launch_factor(P, mode, p, lr, lam, (hipStream_t)stream), "factor pass");
+  return hip_status(launch_factor(P, mode, p, scratch_of(P, p), lr, lam, (hipStream_t)stream), "factor pass");
 }
 
 extern "C" ft_status ft_factor_epoch(const ft_plan* P, const ft_params* p, double lr, double lam, void* stream) {
   FT_TRY(check_plan(P));
   FT_TRY(check_params(P, p));
+  FT_TRY(check_scratch(P, p));
   FT_TRY(check_lr(lr, lam));
   hipStream_t s = (hipStream_t)stream;
+  const Scratch S = scratch_of(P, p);
   for (int m = 0; m < P->N; ++m) {
-    FT_TRY(hip_status(launch_factor(P, m, p, lr, lam, s), "factor pass"));
+    FT_TRY(hip_status(launch_factor(P, m, p, S, lr, lam, s), "factor pass"));
     FT_TRY(hip_status(launch_refresh(P, m, p, s), "refresh"));
   }
   return FT_OK;
@@ -117,30 +131,31 @@ extern "C" ft_status ft_factor_epoch(const ft_plan* P, const ft_params* p, doubl
 extern "C" ft_status ft_core_grad(const ft_plan* P, const ft_params* p, int32_t mode, float* d_G, void* stream) {
   FT_TRY(check_plan(P));
   FT_TRY(check_params(P, p));
+  FT_TRY(check_scratch(P, p));
   FT_TRY(check_mode(P, mode));
   if (!d_G) return fail(FT_ERR_ARG, "null output");
-  hipStream_t s = (hipStream_t)stream;
-  FT_TRY(hip_status(launch_core_grad(P, mode, p, s), "core gradient"));
-  return hip_status(hipMemcpyAsync(d_G, P->gbuf, sizeof(float) * P->J * P->R, hipMemcpyDeviceToDevice, s),
-                    "copy gradient");
+  return hip_status(launch_core_grad(P, mode, p, scratch_of(P, p), d_G, (hipStream_t)stream), "core gradient");
 }
 
 extern "C" ft_status ft_core_pass(const ft_plan* P, const ft_params* p, int32_t mode, double lr, double lam,
                                   void* stream) {
   FT_TRY(check_plan(P));
   FT_TRY(check_params(P, p));
+  FT_TRY(check_scratch(P, p));
   FT_TRY(check_mode(P, mode));
   FT_TRY(check_lr(lr, lam));
-  return hip_status(launch_core_update(P, mode, p, lr, lam, nullptr, (hipStream_t)stream), "core pass");
+  return hip_status(launch_core_update(P, mode, p, scratch_of(P, p), lr, lam, (hipStream_t)stream), "core pass");
 }
 
 extern "C" ft_status ft_core_epoch(const ft_plan* P, const ft_params* p, double lr, double lam, void* stream) {
   FT_TRY(check_plan(P));
   FT_TRY(check_params(P, p));
+  FT_TRY(check_scratch(P, p));
   FT_TRY(check_lr(lr, lam));
   hipStream_t s = (hipStream_t)stream;
+  const Scratch S = scratch_of(P, p);
   for (int m = 0; m < P->N; ++m) {
-    FT_TRY(hip_status(launch_core_update(P, m, p, lr, lam, nullptr, s), "core pass"));
+    FT_TRY(hip_status(launch_core_update(P, m, p, S, lr, lam, s), "core pass"));
     FT_TRY(hip_status(launch_refresh(P, m, p, s), "refresh"));
   }
   return FT_OK;
@@ -156,8 +171,9 @@ extern "C" ft_status ft_loss(const ft_plan* P, const ft_params* p, double lam_a,
                              void* stream) {
   FT_TRY(check_plan(P));
   FT_TRY(check_params(P, p));
+  FT_TRY(check_scratch(P, p));
   if (!d_out4) return fail(FT_ERR_ARG, "null output");
-  return hip_status(launch_loss(P, p, lam_a, lam_b, d_out4, (hipStream_t)stream), "loss");
+  return hip_status(launch_loss(P, p, scratch_of(P, p), lam_a, lam_b, d_out4, (hipStream_t)stream), "loss");
 }
 
 extern "C" ft_status ft_forward(const ft_plan* P, const ft_params* p, float* d_out, void* stream) {
@@ -165,19 +181,20 @@ extern "C" ft_status ft_forward(const ft_plan* P, const ft_params* p, float* d_o
   FT_TRY(check_params(P, p));
   if (!d_out) return fail(FT_ERR_ARG, "null output");
   if (!(P->desc.flags & FT_WITH_PERM)) return fail(FT_ERR_STATE, "ft_forward needs a plan built with FT_WITH_PERM");
-  return hip_status(launch_forward(P, p, d_out, (hipStream_t)stream), "forward");
+  return hip_status(launch_forward(P, p, Scratch{}, d_out, (hipStream_t)stream), "forward");
 }
 
 extern "C" ft_status ft_grad(const ft_plan* P, const ft_params* p, const float* d_upstream, float* const* d_gA,
                              float* const* d_gB, void* stream) {
   FT_TRY(check_plan(P));
   FT_TRY(check_params(P, p));
+  FT_TRY(check_scratch(P, p));
   if (!d_gA || !d_gB) return fail(FT_ERR_ARG, "null gradient arrays");
   for (int n = 0; n < P->N; ++n)
     if (!d_gA[n] || !d_gB[n]) return fail(FT_ERR_ARG, "null gradient pointer");
   if (d_upstream && !(P->desc.flags & FT_WITH_PERM))
     return fail(FT_ERR_STATE, "an upstream gradient needs a plan built with FT_WITH_PERM");
-  return hip_status(launch_grad(P, p, d_upstream, d_gA, d_gB, (hipStream_t)stream), "gradient");
+  return hip_status(launch_grad(P, p, scratch_of(P, p), d_upstream, d_gA, d_gB, (hipStream_t)stream), "gradient");
 }
 
 static void prof_clear(ft_plan* P) {

@@ -16,8 +16,15 @@ namespace {
 // Steps past the end of an item use w = 0 and no decay, which leaves every
 // state unchanged, so the wavefront needs no divergent control flow.
 
+// Byte offset of row i of a C table, unsigned 32-bit: plan creation refuses
+// I_n * R * 4 >= 2^31, so the product never wraps.
+template <int R, class T>
+__device__ __forceinline__ uint32_t row_bytes(int32_t i) {
+  return (uint32_t)i * (uint32_t)(R * sizeof(T));
+}
+
 // value at byte offset `off` of a C table (uniform base + 32-bit offset: the
-// scalar-base addressing form; every table is far below 4 GB)
+// scalar-base addressing form)
 template <class T>
 __device__ __forceinline__ float at_byte(const T* base, uint32_t off) {
   return to_f(*reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off));
@@ -95,7 +102,7 @@ __global__ __launch_bounds__(256) void k_fiber_g(const int32_t* __restrict__ fib
     const int64_t f = min(f0 + l, nfib - 1);
 #pragma unroll
     for (int k = 0; k < N - 1; ++k)
-      ixb[b][k] = len[b] > 0 ? fib_idx[(int64_t)k * nfib + f] * (int)(R * sizeof(T)) : 0;
+      ixb[b][k] = len[b] > 0 ? (int)row_bytes<R, T>(fib_idx[(int64_t)k * nfib + f]) : 0;
   }
   float w[FB][16][RE];
 #pragma unroll
@@ -180,7 +187,7 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
     } else {
 #pragma unroll
       for (int k = 0; k < N - 1; ++k)
-        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (NC ? 1 : (int)(R * sizeof(T))) : 0;
+        ix[k] = it.len > 0 ? (NC ? idx[(int64_t)k * nnz + p] : (int)row_bytes<R, T>(idx[(int64_t)k * nnz + p])) : 0;
     }
   };
   auto stage_b = [&](int t0, const int (&ix)[NI], float (&w)[16][WD]) {
@@ -364,7 +371,7 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
       int ix[N - 1];
 #pragma unroll
       for (int k = 0; k < N - 1; ++k)
-        ix[k] = it.len > 0 ? idx[(int64_t)k * nnz + p] * (NC ? 1 : (int)(R * sizeof(T))) : 0;
+        ix[k] = it.len > 0 ? (NC ? idx[(int64_t)k * nnz + p] : (int)row_bytes<R, T>(idx[(int64_t)k * nnz + p])) : 0;
       if constexpr (NC)
         gather_w_nc<N>(nc, Bc, ix, l, t0, it.len, w);
       else
@@ -657,7 +664,8 @@ unsigned factor_blocks(const void* kernel, int64_t n_items) {
 }
 
 template <int N, int J, int R, class T, bool FIB, bool NC = false>
-hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
+hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, const Scratch& S, double lr, double lam,
+                         hipStream_t s) {
   const ModeMeta& M = P->meta[m];
   const ModeDev& D = P->dev[m];
   const CPtrs<N, T> cp = others<N, T>(p, m);
@@ -675,7 +683,7 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr,
     // fiber_batches batches of 16 fibers per 16-lane group, 16 groups per workgroup
     const int64_t per_block = 16 * 16 * fiber_batches<N, R>();
     hipLaunchKernelGGL((k_fiber_g<N, J, R, T>), dim3((unsigned)((M.n_fibers + per_block - 1) / per_block)), dim3(256),
-                       0, s, D.fib_idx, M.n_fibers, cp, Bm, P->gfib);
+                       0, s, D.fib_idx, M.n_fibers, cp, Bm, S.gfib);
   }
   if constexpr (!NC) {
     if (P->relaxed) {
@@ -685,19 +693,19 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr,
         KTimer tm(P, FT_K_FACTOR_APPLY, s);
         hipLaunchKernelGGL((k_factor_apply<N, J, R, T, FIB>), dim3(factor_blocks(nullptr, M.n_apply)), dim3(256), 0,
                            s, D.apply, M.n_apply, D.idx, P->nnz, D.val, cp, Bm, p->A[m], nullptr, flr, c1, D.fid,
-                           P->gfib, nc, P->maps, D.row_ptr, rho);
+                           S.gfib, nc, S.maps, D.row_ptr, rho);
       }
       if (M.n_compose > 0) {
         KTimer tm(P, FT_K_FACTOR_COMPOSE, s);
         hipLaunchKernelGGL((k_factor_apply<N, J, R, T, FIB, false, true>), dim3(factor_blocks(nullptr, M.n_compose)),
-                           dim3(256), 0, s, D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm, p->A[m], P->hvec,
-                           flr, c1, D.fid, P->gfib, nc, P->maps, D.row_ptr, rho);
+                           dim3(256), 0, s, D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm, p->A[m], S.hvec,
+                           flr, c1, D.fid, S.gfib, nc, S.maps, D.row_ptr, rho);
       }
       if (M.n_relax > 0) {
         KTimer tm(P, FT_K_COMBINE, s);
-        double* part = relax_partials(P, m);
+        double* part = relax_partials(P, S, m);
         hipLaunchKernelGGL((k_relaxed_group<J>), dim3((unsigned)M.n_relax_groups), dim3(256), 0, s, D.relax,
-                           P->maps, part);
+                           S.maps, part);
         hipLaunchKernelGGL((k_relaxed_merge<J>), dim3((unsigned)M.n_relax), dim3(256), 0, s,
                            D.relax + M.n_relax_groups, part, p->A[m], lr, rho);
       }
@@ -708,50 +716,52 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, double lr,
     KTimer tm(P, FT_K_FACTOR_COMPOSE, s);
     hipLaunchKernelGGL((k_factor_compose<N, J, R, T, FIB, NC>),
                        dim3(factor_blocks((const void*)k_factor_compose<N, J, R, T, FIB, NC>, M.n_compose)), dim3(256),
-                       0, s, D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm, P->maps, P->map_scale, flr, c1, gp,
-                       rho, D.fid, P->gfib, nc);
+                       0, s, D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm, S.maps, S.map_scale, flr, c1, gp,
+                       rho, D.fid, S.gfib, nc);
   }
   if (M.n_apply > 0) {
     KTimer tm(P, FT_K_FACTOR_APPLY, s);
     hipLaunchKernelGGL((k_factor_apply<N, J, R, T, FIB, NC>),
                        dim3(factor_blocks((const void*)k_factor_apply<N, J, R, T, FIB, NC>, M.n_apply)), dim3(256), 0,
-                       s, D.apply, M.n_apply, D.idx, P->nnz, D.val, cp, Bm, p->A[m], P->hvec, flr, c1, D.fid, P->gfib,
-                       nc, P->maps, D.row_ptr, rho);
+                       s, D.apply, M.n_apply, D.idx, P->nnz, D.val, cp, Bm, p->A[m], S.hvec, flr, c1, D.fid, S.gfib,
+                       nc, S.maps, D.row_ptr, rho);
   }
   for (size_t L = 0; L < M.level_len.size(); ++L) {
     KTimer tm(P, FT_K_COMBINE, s);
     const int64_t nc = M.level_ncomp[L], nf = M.level_len[L] - nc;
     if (nc > 0)
-      hipLaunchKernelGGL((k_combine<J>), dim3((unsigned)nc), dim3(256), 0, s, D.levels + M.level_off[L], P->maps,
-                         P->map_scale);
+      hipLaunchKernelGGL((k_combine<J>), dim3((unsigned)nc), dim3(256), 0, s, D.levels + M.level_off[L], S.maps,
+                         S.map_scale);
     if (nf > 0)
       hipLaunchKernelGGL((k_combine_final<J>), dim3((unsigned)((nf + 15) / 16)), dim3(256), 0, s,
-                         D.levels + M.level_off[L] + nc, nf, P->maps, P->map_scale, P->hvec, p->A[m]);
+                         D.levels + M.level_off[L] + nc, nf, S.maps, S.map_scale, S.hvec, p->A[m]);
   }
   return hipGetLastError();
 }
 
 template <int N, int J, int R, class T>
-hipError_t factor_impl(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
+hipError_t factor_impl(const ft_plan* P, int m, const ft_params* p, const Scratch& S, double lr, double lam,
+                       hipStream_t s) {
   if (P->no_c_cache) {
     if constexpr (N == 3 && J == 16 && R == 16 && std::is_same<T, float>::value)
-      return factor_launch<N, J, R, T, false, true>(P, m, p, lr, lam, s);
+      return factor_launch<N, J, R, T, false, true>(P, m, p, S, lr, lam, s);
     else
       return hipErrorInvalidValue;  // rejected at plan creation and in the parameter checks
   }
-  return P->meta[m].use_fiber ? factor_launch<N, J, R, T, true>(P, m, p, lr, lam, s)
-                              : factor_launch<N, J, R, T, false>(P, m, p, lr, lam, s);
+  return P->meta[m].use_fiber ? factor_launch<N, J, R, T, true>(P, m, p, S, lr, lam, s)
+                              : factor_launch<N, J, R, T, false>(P, m, p, S, lr, lam, s);
 }
 
 }  // namespace
 
 int max_fanin(int J) { return J <= 8 ? combine_fanin<8>() : J <= 16 ? combine_fanin<16>() : combine_fanin<32>(); }
 
-hipError_t launch_factor(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s) {
+hipError_t launch_factor(const ft_plan* P, int m, const ft_params* p, const Scratch& S, double lr, double lam,
+                         hipStream_t s) {
 #define X(n, j, r)                                                                             \
   case key(n, j, r):                                                                           \
-    return bf16(p) ? factor_impl<n, j, r, uint16_t>(P, m, p, lr, lam, s)                      \
-                   : factor_impl<n, j, r, float>(P, m, p, lr, lam, s);
+    return bf16(p) ? factor_impl<n, j, r, uint16_t>(P, m, p, S, lr, lam, s)                   \
+                   : factor_impl<n, j, r, float>(P, m, p, S, lr, lam, s);
   FT_DISPATCH()
 #undef X
 }

@@ -77,6 +77,49 @@ struct ModeDev {
   int32_t* fib_idx = nullptr;
 };
 
+// Byte offsets of a mode's arrays in the caller's plan workspace (SIZE_MAX:
+// the array is empty and its device pointer stays null).
+struct ModeOff {
+  size_t row_ptr, idx, val, perm, compose, apply, levels, relax, segs, seg_ptr, fid, fib_idx;
+};
+
+// Every array in a device workspace starts on this boundary.
+constexpr size_t kAlign = 256;
+
+// Sequential layout of arrays in one device buffer.
+struct Layout {
+  size_t bytes = 0;
+  size_t add(size_t n) {
+    if (n == 0) return SIZE_MAX;
+    const size_t o = (bytes + kAlign - 1) / kAlign * kAlign;
+    bytes = o + n;
+    return o;
+  }
+};
+
+// Scratch of one parameter set (ft_params.scratch): what the passes write
+// between launches.  Byte offsets, sized for the largest mode of the plan.
+struct ScratchOff {
+  size_t maps = SIZE_MAX;       // float: chunk maps (J^2 + J each; FT_RELAXED: increments, then FP64 group records)
+  size_t map_scale = SIZE_MAX;  // double: rho^length of each map
+  size_t hvec = SIZE_MAX;       // float: head vectors of long rows (J each)
+  size_t partials = SIZE_MAX;   // float: per-workgroup J x R partial sums, then their folds
+  size_t dpartials = SIZE_MAX;  // double: per-workgroup FP64 loss partials, then the regulariser partials
+  size_t tseg = SIZE_MAX;       // float: per-segment sums of the gradient pass (R each)
+  size_t gfib = SIZE_MAX;       // float: the shared g of each fiber (J each)
+};
+
+// Device pointers of a parameter set's scratch for one call.
+struct Scratch {
+  float* maps = nullptr;
+  double* map_scale = nullptr;
+  float* hvec = nullptr;
+  float* partials = nullptr;
+  double* dpartials = nullptr;
+  float* tseg = nullptr;
+  float* gfib = nullptr;
+};
+
 struct ModeMeta {
   int64_t I = 0;
   int64_t n_compose = 0;  // padded counts
@@ -114,17 +157,12 @@ struct ft_plan {
   std::vector<ft::ModeDev> dev;
   bool host_valid = false;
   bool uploaded = false;
-  // scratch shared by all modes (sized for the largest)
-  float* maps = nullptr;       // map slots (level ping-pong region 0 and 1)
-  double* map_scale = nullptr; // rho^(elements) of each map
-  int64_t maps_region1 = 0;    // slot offset of region 1
-  float* hvec = nullptr;       // heavy rows' head vectors
-  float* partials = nullptr;   // per-workgroup partial sums (core/grad)
-  double* dpartials = nullptr; // per-workgroup FP64 partial sums (loss)
-  float* tseg = nullptr;       // per-segment row sums (gradient)
-  float* gbuf = nullptr;       // J x R gradient buffer
-  float* gfib = nullptr;       // fibers x J: the shared g of each fiber (factor pass)
+  // device arrays of the plan: byte offsets in the caller's workspace (ft_plan_upload)
+  std::vector<ft::ModeOff> off;
   size_t device_bytes = 0;
+  // scratch every parameter set brings (ft_params.scratch)
+  ft::ScratchOff soff;
+  size_t scratch_bytes = 0;
   // kernel timing (ft_profile_enable); launches on a const plan append to it
   mutable bool prof_on = false;
   mutable std::vector<ft_prof_rec> prof;
@@ -139,8 +177,8 @@ constexpr int kPartials = 2048;  // max workgroups of the reduction kernels
 constexpr int kSegLen = 512;     // max elements per segment
 constexpr int kRelaxGroup = 256; // chunks per level-1 group of the relaxed merge
 
-// FT_RELAXED scratch in P->maps: J + 1 floats per chunk slot, then (8-byte
-// aligned) J + 1 doubles per level-1 group
+// FT_RELAXED scratch in the map region: J + 1 floats per chunk slot, then
+// (8-byte aligned) J + 1 doubles per level-1 group
 inline int64_t relax_incr_floats(int64_t n_maps, int J) { return (n_maps * (J + 1) + 1) / 2 * 2; }
 
 // Brackets one kernel launch with events when timing is enabled on the plan.
@@ -162,21 +200,27 @@ struct KTimer {
   }
 };
 
-inline double* relax_partials(const ft_plan* P, int m) {
-  return reinterpret_cast<double*>(P->maps + relax_incr_floats(P->meta[m].n_maps, P->J));
+inline double* relax_partials(const ft_plan* P, const Scratch& S, int m) {
+  return reinterpret_cast<double*>(S.maps + relax_incr_floats(P->meta[m].n_maps, P->J));
 }
 
+// Scratch pointers of a parameter set (its buffer checked by the caller).
+Scratch scratch_of(const ft_plan* P, const ft_params* p);
+
 hipError_t launch_refresh(const ft_plan* P, int n, const ft_params* p, hipStream_t s);
-hipError_t launch_factor(const ft_plan* P, int m, const ft_params* p, double lr, double lam, hipStream_t s);
-hipError_t launch_core_grad(const ft_plan* P, int m, const ft_params* p, hipStream_t s);  // result in P->gbuf
-hipError_t launch_core_update(const ft_plan* P, int m, const ft_params* p, double lr, double lam, float* G_out,
+hipError_t launch_factor(const ft_plan* P, int m, const ft_params* p, const Scratch& S, double lr, double lam,
+                         hipStream_t s);
+hipError_t launch_core_grad(const ft_plan* P, int m, const ft_params* p, const Scratch& S, float* G_out,
+                            hipStream_t s);
+hipError_t launch_core_update(const ft_plan* P, int m, const ft_params* p, const Scratch& S, double lr, double lam,
                               hipStream_t s);
-hipError_t launch_loss(const ft_plan* P, const ft_params* p, double lam_a, double lam_b, double* out4, hipStream_t s);
+hipError_t launch_loss(const ft_plan* P, const ft_params* p, const Scratch& S, double lam_a, double lam_b,
+                       double* out4, hipStream_t s);
 hipError_t launch_predict(const ft_plan* P, const ft_params* p, const int32_t* coords, int64_t q, float* out,
                           hipStream_t s);
-hipError_t launch_forward(const ft_plan* P, const ft_params* p, float* out, hipStream_t s);
-hipError_t launch_grad(const ft_plan* P, const ft_params* p, const float* upstream, float* const* gA,
-                       float* const* gB, hipStream_t s);
+hipError_t launch_forward(const ft_plan* P, const ft_params* p, const Scratch& S, float* out, hipStream_t s);
+hipError_t launch_grad(const ft_plan* P, const ft_params* p, const Scratch& S, const float* upstream,
+                       float* const* gA, float* const* gB, hipStream_t s);
 bool supported(int N, int J, int R);
 int max_fanin(int J);  // largest combine fan-in the kernels hold in LDS
 }  // namespace ft

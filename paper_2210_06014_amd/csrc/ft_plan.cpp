@@ -352,6 +352,71 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   return FT_OK;
 }
 
+// Offsets of the plan's device arrays in the caller's workspace, and the
+// scratch layout every parameter set brings (sized for the largest mode).
+static void layout(ft_plan* P) {
+  const int N = P->N, J = P->J, R = P->R;
+  const bool perm = (P->desc.flags & FT_WITH_PERM) != 0;
+  Layout L;
+  P->off.assign(N, ModeOff{});
+  int64_t max_slots = 1, max_heavy = 1, max_segs = 1, max_fib = 0, map_floats = 0;
+  for (int m = 0; m < N; ++m) {
+    const ModeHost& H = P->host[m];
+    const ModeMeta& M = P->meta[m];
+    ModeOff& o = P->off[m];
+    size_t nlev = 0;
+    for (auto& v : H.levels) nlev += v.size();
+    o.row_ptr = L.add(H.row_ptr.size() * sizeof(int64_t));
+    o.idx = L.add(H.idx.size() * sizeof(int32_t));
+    o.val = L.add(H.val.size() * sizeof(float));
+    o.perm = L.add(perm ? H.perm.size() * sizeof(int32_t) : 0);
+    o.compose = L.add(H.compose.size() * sizeof(FItem));
+    o.apply = L.add(H.apply.size() * sizeof(FItem));
+    o.levels = L.add(nlev * sizeof(CItem));
+    o.relax = L.add(P->relaxed ? H.relax.size() * sizeof(CItem) : 0);
+    o.segs = L.add(H.segs.size() * sizeof(Seg));
+    o.seg_ptr = L.add(H.seg_ptr.size() * sizeof(int64_t));
+    o.fid = L.add(M.use_fiber ? H.fid.size() * sizeof(int32_t) : 0);
+    o.fib_idx = L.add(M.use_fiber ? H.fib_idx.size() * sizeof(int32_t) : 0);
+    if (M.use_fiber) max_fib = std::max(max_fib, M.n_fibers);
+    max_slots = std::max(max_slots, M.n_maps + M.n_level_out0);
+    max_heavy = std::max(max_heavy, M.n_heavy);
+    max_segs = std::max(max_segs, M.n_segs);
+    map_floats = std::max(map_floats, max_slots * (J * J + J));
+    if (P->relaxed)
+      map_floats = std::max(map_floats, relax_incr_floats(M.n_maps, J) + 2 * M.n_relax_groups * (J + 1));
+  }
+  P->device_bytes = L.bytes;
+  Layout S;
+  ScratchOff& so = P->soff;
+  so.maps = S.add((size_t)std::max<int64_t>(map_floats, 1) * sizeof(float));
+  so.map_scale = S.add((size_t)max_slots * sizeof(double));
+  so.hvec = S.add((size_t)max_heavy * J * sizeof(float));
+  so.partials = S.add((size_t)(kPartials + kPartials / 32 + 1) * J * R * sizeof(float));
+  so.dpartials = S.add(((size_t)kPartials + 2 * FT_MAX_ORDER * 256) * sizeof(double));
+  so.tseg = S.add((size_t)max_segs * R * sizeof(float));
+  so.gfib = S.add((size_t)max_fib * J * sizeof(float));
+  P->scratch_bytes = S.bytes;
+}
+
+template <class T>
+static T* at(void* base, size_t off) {
+  return off == SIZE_MAX ? nullptr : reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+Scratch scratch_of(const ft_plan* P, const ft_params* p) {
+  Scratch S;
+  const ScratchOff& o = P->soff;
+  S.maps = at<float>(p->scratch, o.maps);
+  S.map_scale = at<double>(p->scratch, o.map_scale);
+  S.hvec = at<float>(p->scratch, o.hvec);
+  S.partials = at<float>(p->scratch, o.partials);
+  S.dpartials = at<double>(p->scratch, o.dpartials);
+  S.tseg = at<float>(p->scratch, o.tseg);
+  S.gfib = at<float>(p->scratch, o.gfib);
+  return S;
+}
+
 }  // namespace ft
 
 using namespace ft;
@@ -367,6 +432,10 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
     if (d->dims[n] < 1 || d->dims[n] > 0x7FFFFFFF) return fail(FT_ERR_SHAPE, "dimension out of range");
     if (d->J[n] != d->J[0]) return fail(FT_ERR_UNSUPPORTED, "all J_n must be equal");
   }
+  // the kernels gather C rows by 32-bit byte offsets from the table's base
+  for (int n = 0; n < d->order; ++n)
+    if (d->dims[n] * (int64_t)d->R * 4 >= ((int64_t)1 << 31))
+      return fail(FT_ERR_SHAPE, "mode " + std::to_string(n) + ": I_n * R * 4 bytes must be below 2^31");
   if (!supported(d->order, d->J[0], d->R))
     return fail(FT_ERR_UNSUPPORTED, "no kernels compiled for order " + std::to_string(d->order) + ", J " +
                                         std::to_string(d->J[0]) + ", R " + std::to_string(d->R));
@@ -428,6 +497,7 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
       return s;
     }
   }
+  layout(P);
   P->host_valid = true;
   *out = P;
   return FT_OK;
@@ -435,94 +505,69 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
 
 namespace {
 template <class T>
-hipError_t upload(T** dst, const std::vector<T>& src, size_t& bytes) {
-  *dst = nullptr;
-  if (src.empty()) return hipSuccess;
-  hipError_t e = hipMalloc((void**)dst, src.size() * sizeof(T));
-  if (e != hipSuccess) return e;
-  bytes += src.size() * sizeof(T);
-  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
-}
-template <class T>
-hipError_t alloc(T** dst, size_t count, size_t& bytes) {
-  *dst = nullptr;
-  if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)dst, count * sizeof(T));
-  if (e == hipSuccess) bytes += count * sizeof(T);
-  return e;
-}
-void free_dev(ft_plan* P) {
-  for (auto& D : P->dev) {
-    (void)hipFree(D.row_ptr); (void)hipFree(D.idx); (void)hipFree(D.val); (void)hipFree(D.perm);
-    (void)hipFree(D.compose); (void)hipFree(D.fid); (void)hipFree(D.fib_idx);
-    (void)hipFree(D.apply); (void)hipFree(D.levels); (void)hipFree(D.segs); (void)hipFree(D.seg_ptr);
-    (void)hipFree(D.relax);
-    D = ModeDev{};
-  }
-  (void)hipFree(P->maps); (void)hipFree(P->map_scale); (void)hipFree(P->hvec); (void)hipFree(P->partials);
-  (void)hipFree(P->dpartials);
-  (void)hipFree(P->tseg); (void)hipFree(P->gbuf); (void)hipFree(P->gfib);
-  P->maps = nullptr; P->map_scale = nullptr; P->hvec = nullptr; P->partials = nullptr; P->dpartials = nullptr;
-  P->tseg = nullptr; P->gbuf = nullptr; P->gfib = nullptr;
-  P->device_bytes = 0;
-  P->uploaded = false;
+hipError_t copy_in(void* base, size_t off, const std::vector<T>& src, hipStream_t s) {
+  if (off == SIZE_MAX || src.empty()) return hipSuccess;
+  return hipMemcpyAsync(static_cast<char*>(base) + off, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 }  // namespace
 
-extern "C" ft_status ft_plan_upload(ft_plan* P, void* stream) {
+extern "C" ft_status ft_plan_query(const ft_plan* P, size_t* device_bytes, size_t* scratch_bytes) {
   if (!P) return fail(FT_ERR_ARG, "null plan");
-  if (P->uploaded) return FT_OK;
-  if (!P->host_valid) return fail(FT_ERR_STATE, "host plan already released");
-  (void)stream;
-  size_t bytes = 0;
+  if (device_bytes) *device_bytes = P->device_bytes;
+  if (scratch_bytes) *scratch_bytes = P->scratch_bytes;
+  return FT_OK;
+}
+
+extern "C" ft_status ft_plan_upload(ft_plan* P, void* ws, size_t ws_bytes, void* stream) {
+  if (!P) return fail(FT_ERR_ARG, "null plan");
+  if (!P->host_valid) return fail(FT_ERR_STATE, "plan already uploaded and its host copy released");
+  if (!ws || ws_bytes < P->device_bytes)
+    return fail(FT_ERR_WORKSPACE, "plan workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                      std::to_string(P->device_bytes));
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(FT_ERR_WORKSPACE, "plan workspace not 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSuccess;
-  int64_t max_slots = 1, max_heavy = 1, max_segs = 1, max_fib = 0;
+  // the int32 permutations and the concatenated combine levels are staged
+  // here and must live until the copies have completed (the wait below)
+  std::vector<std::vector<int32_t>> perm32(P->N);
+  std::vector<std::vector<CItem>> levels(P->N);
   for (int m = 0; m < P->N && e == hipSuccess; ++m) {
-    ModeHost& H = P->host[m];
+    const ModeHost& H = P->host[m];
+    const ModeOff& o = P->off[m];
+    if (o.perm != SIZE_MAX) perm32[m].assign(H.perm.begin(), H.perm.end());
+    for (auto& L : H.levels) levels[m].insert(levels[m].end(), L.begin(), L.end());
+    e = copy_in(ws, o.row_ptr, H.row_ptr, s);
+    if (e == hipSuccess) e = copy_in(ws, o.idx, H.idx, s);
+    if (e == hipSuccess) e = copy_in(ws, o.val, H.val, s);
+    if (e == hipSuccess) e = copy_in(ws, o.perm, perm32[m], s);
+    if (e == hipSuccess) e = copy_in(ws, o.compose, H.compose, s);
+    if (e == hipSuccess) e = copy_in(ws, o.apply, H.apply, s);
+    if (e == hipSuccess) e = copy_in(ws, o.levels, levels[m], s);
+    if (e == hipSuccess) e = copy_in(ws, o.relax, H.relax, s);
+    if (e == hipSuccess) e = copy_in(ws, o.segs, H.segs, s);
+    if (e == hipSuccess) e = copy_in(ws, o.seg_ptr, H.seg_ptr, s);
+    if (e == hipSuccess) e = copy_in(ws, o.fid, H.fid, s);
+    if (e == hipSuccess) e = copy_in(ws, o.fib_idx, H.fib_idx, s);
+  }
+  const hipError_t w = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = w;
+  if (e != hipSuccess) return fail(FT_ERR_HIP, std::string("plan upload failed: ") + hipGetErrorString(e));
+  for (int m = 0; m < P->N; ++m) {
+    const ModeOff& o = P->off[m];
     ModeDev& D = P->dev[m];
-    ModeMeta& M = P->meta[m];
-    e = upload(&D.row_ptr, H.row_ptr, bytes);
-    if (e == hipSuccess) e = upload(&D.idx, H.idx, bytes);
-    if (e == hipSuccess) e = upload(&D.val, H.val, bytes);
-    if (e == hipSuccess && (P->desc.flags & FT_WITH_PERM)) {
-      std::vector<int32_t> p32(H.perm.begin(), H.perm.end());
-      e = upload(&D.perm, p32, bytes);
-    }
-    if (e == hipSuccess) e = upload(&D.compose, H.compose, bytes);
-    if (e == hipSuccess) e = upload(&D.apply, H.apply, bytes);
-    if (e == hipSuccess) {
-      std::vector<CItem> all;
-      for (auto& L : H.levels) all.insert(all.end(), L.begin(), L.end());
-      e = upload(&D.levels, all, bytes);
-    }
-    if (e == hipSuccess && P->relaxed) e = upload(&D.relax, H.relax, bytes);
-    if (e == hipSuccess) e = upload(&D.segs, H.segs, bytes);
-    if (e == hipSuccess) e = upload(&D.seg_ptr, H.seg_ptr, bytes);
-    if (e == hipSuccess && M.use_fiber) e = upload(&D.fid, H.fid, bytes);
-    if (e == hipSuccess && M.use_fiber) e = upload(&D.fib_idx, H.fib_idx, bytes);
-    if (M.use_fiber) max_fib = std::max(max_fib, M.n_fibers);
-    max_slots = std::max(max_slots, M.n_maps + M.n_level_out0);
-    max_heavy = std::max(max_heavy, M.n_heavy);
-    max_segs = std::max(max_segs, M.n_segs);
+    D.row_ptr = at<int64_t>(ws, o.row_ptr);
+    D.idx = at<int32_t>(ws, o.idx);
+    D.val = at<float>(ws, o.val);
+    D.perm = at<int32_t>(ws, o.perm);
+    D.compose = at<FItem>(ws, o.compose);
+    D.apply = at<FItem>(ws, o.apply);
+    D.levels = at<CItem>(ws, o.levels);
+    D.relax = at<CItem>(ws, o.relax);
+    D.segs = at<Seg>(ws, o.segs);
+    D.seg_ptr = at<int64_t>(ws, o.seg_ptr);
+    D.fid = at<int32_t>(ws, o.fid);
+    D.fib_idx = at<int32_t>(ws, o.fib_idx);
   }
-  const int J = P->J, R = P->R;
-  int64_t map_floats = max_slots * (J * J + J);
-  for (int m = 0; m < P->N && P->relaxed; ++m)
-    map_floats = std::max(map_floats, relax_incr_floats(P->meta[m].n_maps, J) + 2 * P->meta[m].n_relax_groups * (J + 1));
-  if (e == hipSuccess) e = alloc(&P->maps, (size_t)map_floats, bytes);
-  if (e == hipSuccess) e = alloc(&P->map_scale, (size_t)max_slots, bytes);
-  if (e == hipSuccess) e = alloc(&P->hvec, (size_t)max_heavy * J, bytes);
-  if (e == hipSuccess) e = alloc(&P->partials, (size_t)(kPartials + kPartials / 32 + 1) * J * R, bytes);
-  if (e == hipSuccess) e = alloc(&P->dpartials, (size_t)kPartials + 2 * FT_MAX_ORDER * 256, bytes);
-  if (e == hipSuccess) e = alloc(&P->tseg, (size_t)max_segs * R, bytes);
-  if (e == hipSuccess) e = alloc(&P->gbuf, (size_t)J * R, bytes);
-  if (e == hipSuccess && max_fib > 0) e = alloc(&P->gfib, (size_t)max_fib * J, bytes);
-  if (e != hipSuccess) {
-    free_dev(P);
-    return fail(FT_ERR_HIP, std::string("device allocation or copy failed: ") + hipGetErrorString(e));
-  }
-  for (int m = 0; m < P->N; ++m) P->dev[m].perm = (P->desc.flags & FT_WITH_PERM) ? P->dev[m].perm : nullptr;
-  P->device_bytes = bytes;
   P->uploaded = true;
   if (!(P->desc.flags & FT_KEEP_HOST)) {
     for (auto& H : P->host) H = ModeHost{};
@@ -531,25 +576,12 @@ extern "C" ft_status ft_plan_upload(ft_plan* P, void* stream) {
   return FT_OK;
 }
 
-extern "C" void ft_plan_destroy(ft_plan* P) {
-  if (!P) return;
-  if (P->uploaded) {
-    (void)hipDeviceSynchronize();
-    free_dev(P);
-  }
-  delete P;
-}
+extern "C" void ft_plan_destroy(ft_plan* P) { delete P; }
 
 extern "C" ft_status ft_plan_mode_info(const ft_plan* P, int32_t mode, ft_mode_info* info) {
   if (!P || !info) return fail(FT_ERR_ARG, "null argument");
   if (mode < 0 || mode >= P->N) return fail(FT_ERR_ARG, "mode out of range");
   *info = P->meta[mode].info;
-  return FT_OK;
-}
-
-extern "C" ft_status ft_plan_device_bytes(const ft_plan* P, size_t* bytes) {
-  if (!P || !bytes) return fail(FT_ERR_ARG, "null argument");
-  *bytes = P->device_bytes;
   return FT_OK;
 }
 

@@ -508,13 +508,13 @@ __global__ __launch_bounds__(256) void k_predict(const int32_t* __restrict__ coo
 }
 
 
-hipError_t reduce_partials(const ft_plan* P, int nparts, float* Bm, float* Gout, float lr, float lam, float inv,
-                           int update, hipStream_t s) {
+hipError_t reduce_partials(const ft_plan* P, const Scratch& S, int nparts, float* Bm, float* Gout, float lr,
+                           float lam, float inv, int update, hipStream_t s) {
   KTimer tm(P, FT_K_REDUCE, s);
   const int JR = P->J * P->R;
   const int nfold = (nparts + kFold - 1) / kFold;
-  float* folded = P->partials + (int64_t)kPartials * JR;
-  if (nfold > 0) hipLaunchKernelGGL(k_fold_partials, dim3(nfold), dim3(256), 0, s, P->partials, nparts, JR, folded);
+  float* folded = S.partials + (int64_t)kPartials * JR;
+  if (nfold > 0) hipLaunchKernelGGL(k_fold_partials, dim3(nfold), dim3(256), 0, s, S.partials, nparts, JR, folded);
   hipLaunchKernelGGL(k_reduce_update, dim3((JR + 255) / 256), dim3(256), 0, s, folded, nfold, JR, Bm, Gout, lr, lam,
                      inv, update);
   return hipGetLastError();
@@ -528,33 +528,35 @@ int seg_blocks(const void* kernel, int64_t nseg) {
 }
 
 template <int N, int J, int R, class T>
-hipError_t segsum_impl(const ft_plan* P, int m, const ft_params* p, int mode, const float* up, float* tseg,
-                       hipStream_t s, int* nblocks) {
+hipError_t segsum_impl(const ft_plan* P, int m, const ft_params* p, float* partials, int mode, const float* up,
+                       float* tseg, hipStream_t s, int* nblocks) {
   const ModeMeta& M = P->meta[m];
   const ModeDev& D = P->dev[m];
   const CPtrs<N, T> cp = others<N, T>(p, m);
   const T* Cm = Store<T>::C(p, m);
   const T* Am = Store<T>::A(p, m);
-  const void* kern = mode == 0 ? (const void*)k_segsum<N, J, R, 0, T>
-                     : mode == 1 ? (const void*)k_segsum<N, J, R, 1, T> : (const void*)k_segsum<N, J, R, 2, T>;
+  // modes 0 and 1 (the core gradient and the gradient of 1/2 sum e^2) launch
+  // the same grid, so their sums run in the same order and one is the exact
+  // negation of the other
+  const void* kern = mode == 2 ? (const void*)k_segsum<N, J, R, 2, T> : (const void*)k_segsum<N, J, R, 0, T>;
   const int nb = seg_blocks(kern, M.n_segs);
   *nblocks = nb;
   KTimer tm(P, FT_K_SEGSUM, s);
   if (mode == 0)
     hipLaunchKernelGGL((k_segsum<N, J, R, 0, T>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val,
-                       cp, Cm, Am, nullptr, nullptr, P->partials, tseg);
+                       cp, Cm, Am, nullptr, nullptr, partials, tseg);
   else if (mode == 1)
     hipLaunchKernelGGL((k_segsum<N, J, R, 1, T>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val,
-                       cp, Cm, Am, nullptr, nullptr, P->partials, tseg);
+                       cp, Cm, Am, nullptr, nullptr, partials, tseg);
   else
     hipLaunchKernelGGL((k_segsum<N, J, R, 2, T>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val,
-                       cp, Cm, Am, up, D.perm, P->partials, tseg);
+                       cp, Cm, Am, up, D.perm, partials, tseg);
   return hipGetLastError();
 }
 
 template <int N, int J, int R, class T>
-hipError_t loss_impl(const ft_plan* P, const ft_params* p, double lam_a, double lam_b, double* out4, float* xout,
-                     hipStream_t s) {
+hipError_t loss_impl(const ft_plan* P, const ft_params* p, double* dpart, double lam_a, double lam_b, double* out4,
+                     float* xout, hipStream_t s) {
   const ModeMeta& M = P->meta[0];
   const ModeDev& D = P->dev[0];
   const CPtrs<N, T> cp = others<N, T>(p, 0);
@@ -562,19 +564,19 @@ hipError_t loss_impl(const ft_plan* P, const ft_params* p, double lam_a, double 
   {
     KTimer tm(P, FT_K_LOSS, s);
     hipLaunchKernelGGL((k_loss<N, R, T>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp,
-                       Store<T>::C(p, 0), out4 ? P->dpartials : nullptr, D.perm, xout);
+                       Store<T>::C(p, 0), out4 ? dpart : nullptr, D.perm, xout);
   }
   if (!out4) return hipGetLastError();
   // the regularisers of Eq. (6) are taken on the FP32 masters
   KTimer tm(P, FT_K_REDUCE, s);
-  double* rpart = P->dpartials + kPartials;
+  double* rpart = dpart + kPartials;
   for (int n = 0; n < N; ++n)
     hipLaunchKernelGGL(k_sumsq, dim3(kSumsqBlocks), dim3(256), 0, s, p->A[n], P->desc.dims[n] * J,
                        rpart + n * kSumsqBlocks);
   for (int n = 0; n < N; ++n)
     hipLaunchKernelGGL(k_sumsq, dim3(kSumsqBlocks), dim3(256), 0, s, p->B[n], (int64_t)J * R,
                        rpart + (N + n) * kSumsqBlocks);
-  hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, s, P->dpartials, nb, rpart, N * kSumsqBlocks,
+  hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, s, dpart, nb, rpart, N * kSumsqBlocks,
                      N * kSumsqBlocks, (double)P->nnz, lam_a, lam_b, out4);
   return hipGetLastError();
 }
@@ -590,29 +592,29 @@ hipError_t predict_impl(const ft_params* p, const int32_t* coords, int64_t q, fl
 }
 
 template <int J, int R, class T>
-hipError_t grad_rows_impl(const ft_plan* P, int m, const ft_params* p, float* gA, hipStream_t s) {
+hipError_t grad_rows_impl(const ft_plan* P, int m, const ft_params* p, const float* tseg, float* gA, hipStream_t s) {
   const int64_t I = P->desc.dims[m];
   const unsigned gb = (unsigned)((I * J + 255) / 256);
   if (gb > 0)
-    hipLaunchKernelGGL((k_grad_rows<J, R, T>), dim3(gb), dim3(256), 0, s, P->dev[m].seg_ptr, P->tseg,
+    hipLaunchKernelGGL((k_grad_rows<J, R, T>), dim3(gb), dim3(256), 0, s, P->dev[m].seg_ptr, tseg,
                        Store<T>::B(p, m), gA, I);
   return hipGetLastError();
 }
 
 }  // namespace
 
-static hipError_t segsum(const ft_plan* P, int m, const ft_params* p, int mode, const float* up, float* tseg,
-                         hipStream_t s, int* nb) {
+static hipError_t segsum(const ft_plan* P, int m, const ft_params* p, float* partials, int mode, const float* up,
+                         float* tseg, hipStream_t s, int* nb) {
 #define X(n, j, r)                                                                             \
   case key(n, j, r):                                                                           \
-    return bf16(p) ? segsum_impl<n, j, r, uint16_t>(P, m, p, mode, up, tseg, s, nb)           \
-                   : segsum_impl<n, j, r, float>(P, m, p, mode, up, tseg, s, nb);
+    return bf16(p) ? segsum_impl<n, j, r, uint16_t>(P, m, p, partials, mode, up, tseg, s, nb) \
+                   : segsum_impl<n, j, r, float>(P, m, p, partials, mode, up, tseg, s, nb);
   FT_DISPATCH()
 #undef X
 }
 
 // core gradient partials without the C cache (N = 3, J = R = 16, FP32 only)
-static hipError_t core_nc(const ft_plan* P, int m, const ft_params* p, hipStream_t s, int* nb) {
+static hipError_t core_nc(const ft_plan* P, int m, const ft_params* p, float* partials, hipStream_t s, int* nb) {
   if (P->N != 3 || P->J != 16 || P->R != 16 || bf16(p)) return hipErrorInvalidValue;
   const ModeMeta& M = P->meta[m];
   const ModeDev& D = P->dev[m];
@@ -626,40 +628,45 @@ static hipError_t core_nc(const ft_plan* P, int m, const ft_params* p, hipStream
   *nb = (int)b;
   KTimer tm(P, FT_K_SEGSUM, s);
   hipLaunchKernelGGL(k_core_nc<3>, dim3((unsigned)b), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, nc,
-                     p->A[m], p->B[m], P->partials);
+                     p->A[m], p->B[m], partials);
   return hipGetLastError();
 }
 
-hipError_t launch_core_grad(const ft_plan* P, int m, const ft_params* p, hipStream_t s) {
+hipError_t launch_core_grad(const ft_plan* P, int m, const ft_params* p, const Scratch& S, float* G_out,
+                            hipStream_t s) {
   int nb = 0;
-  hipError_t e = P->no_c_cache ? core_nc(P, m, p, s, &nb) : segsum(P, m, p, 0, nullptr, nullptr, s, &nb);
+  hipError_t e = P->no_c_cache ? core_nc(P, m, p, S.partials, s, &nb)
+                               : segsum(P, m, p, S.partials, 0, nullptr, nullptr, s, &nb);
   if (e != hipSuccess) return e;
-  return reduce_partials(P, nb, nullptr, P->gbuf, 0.f, 0.f, 0.f, 0, s);
+  return reduce_partials(P, S, nb, nullptr, G_out, 0.f, 0.f, 0.f, 0, s);
 }
 
-hipError_t launch_core_update(const ft_plan* P, int m, const ft_params* p, double lr, double lam, float* G_out,
+hipError_t launch_core_update(const ft_plan* P, int m, const ft_params* p, const Scratch& S, double lr, double lam,
                               hipStream_t s) {
   int nb = 0;
-  hipError_t e = P->no_c_cache ? core_nc(P, m, p, s, &nb) : segsum(P, m, p, 0, nullptr, nullptr, s, &nb);
+  hipError_t e = P->no_c_cache ? core_nc(P, m, p, S.partials, s, &nb)
+                               : segsum(P, m, p, S.partials, 0, nullptr, nullptr, s, &nb);
   if (e != hipSuccess) return e;
   const float inv = P->nnz > 0 ? (float)(1.0 / (double)P->nnz) : 0.f;
-  return reduce_partials(P, nb, p->B[m], G_out, (float)lr, (float)lam, inv, P->nnz > 0 ? 1 : 0, s);
+  return reduce_partials(P, S, nb, p->B[m], nullptr, (float)lr, (float)lam, inv, P->nnz > 0 ? 1 : 0, s);
 }
 
-hipError_t launch_loss(const ft_plan* P, const ft_params* p, double lam_a, double lam_b, double* out4, hipStream_t s) {
+hipError_t launch_loss(const ft_plan* P, const ft_params* p, const Scratch& S, double lam_a, double lam_b,
+                       double* out4, hipStream_t s) {
 #define X(n, j, r)                                                                             \
   case key(n, j, r):                                                                           \
-    return bf16(p) ? loss_impl<n, j, r, uint16_t>(P, p, lam_a, lam_b, out4, nullptr, s)       \
-                   : loss_impl<n, j, r, float>(P, p, lam_a, lam_b, out4, nullptr, s);
+    return bf16(p) ? loss_impl<n, j, r, uint16_t>(P, p, S.dpartials, lam_a, lam_b, out4, nullptr, s) \
+                   : loss_impl<n, j, r, float>(P, p, S.dpartials, lam_a, lam_b, out4, nullptr, s);
   FT_DISPATCH()
 #undef X
 }
 
-hipError_t launch_forward(const ft_plan* P, const ft_params* p, float* out, hipStream_t s) {
+// forward writes no partials (the loss kernel stores xhat only)
+hipError_t launch_forward(const ft_plan* P, const ft_params* p, const Scratch&, float* out, hipStream_t s) {
 #define X(n, j, r)                                                                             \
   case key(n, j, r):                                                                           \
-    return bf16(p) ? loss_impl<n, j, r, uint16_t>(P, p, 0.0, 0.0, nullptr, out, s)            \
-                   : loss_impl<n, j, r, float>(P, p, 0.0, 0.0, nullptr, out, s);
+    return bf16(p) ? loss_impl<n, j, r, uint16_t>(P, p, nullptr, 0.0, 0.0, nullptr, out, s)   \
+                   : loss_impl<n, j, r, float>(P, p, nullptr, 0.0, 0.0, nullptr, out, s);
   FT_DISPATCH()
 #undef X
 }
@@ -674,23 +681,24 @@ hipError_t launch_predict(const ft_plan* P, const ft_params* p, const int32_t* c
 #undef X
 }
 
-hipError_t launch_grad(const ft_plan* P, const ft_params* p, const float* up, float* const* gA, float* const* gB,
-                       hipStream_t s) {
+hipError_t launch_grad(const ft_plan* P, const ft_params* p, const Scratch& S, const float* up, float* const* gA,
+                       float* const* gB, hipStream_t s) {
   for (int m = 0; m < P->N; ++m) {
     int nb = 0;
-    hipError_t e = segsum(P, m, p, up ? 2 : 1, up, P->tseg, s, &nb);
+    hipError_t e = segsum(P, m, p, S.partials, up ? 2 : 1, up, S.tseg, s, &nb);
     if (e != hipSuccess) return e;
     switch (P->J * 64 + P->R) {
 #define X(n_, j, r)                                                                                        \
   case j * 64 + r:                                                                                         \
-    e = bf16(p) ? grad_rows_impl<j, r, uint16_t>(P, m, p, gA[m], s) : grad_rows_impl<j, r, float>(P, m, p, gA[m], s); \
+    e = bf16(p) ? grad_rows_impl<j, r, uint16_t>(P, m, p, S.tseg, gA[m], s)                               \
+                : grad_rows_impl<j, r, float>(P, m, p, S.tseg, gA[m], s);                                 \
     break;
       X(0, 8, 8) X(0, 16, 16) X(0, 32, 32) X(0, 8, 16)
 #undef X
       default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
-    e = reduce_partials(P, nb, nullptr, gB[m], 0.f, 0.f, 0.f, 0, s);
+    e = reduce_partials(P, S, nb, nullptr, gB[m], 0.f, 0.f, 0.f, 0, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

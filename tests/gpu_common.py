@@ -42,11 +42,20 @@ def abs_scale(C_list, coords):
 
 
 def delta_ok(after_gpu, after_orc, before, rel=1e-3, abs_rel=1e-6):
-    """||gpu - oracle|| <= rel ||oracle - before|| + abs_rel ||oracle||; returns (ok, err, bound)."""
-    d = np.linalg.norm(after_orc - before)
-    err = np.linalg.norm(after_gpu - after_orc)
-    bound = rel * d + abs_rel * np.linalg.norm(after_orc)
-    return err <= bound, err, bound
+    """Parity of one pass: ||gpu - oracle|| <= rel ||oracle - before|| + abs_rel ||oracle||, over the whole
+    array and, for a matrix, over every row on its own, so that an error in one row's step (one element
+    mishandled at a chunk, head or combine boundary) cannot hide among the other rows.  Returns
+    (ok, err, bound) of the tightest of these checks (the largest err / bound)."""
+    g, o, b = (np.asarray(x, dtype=np.float64) for x in (after_gpu, after_orc, before))
+    err = [np.linalg.norm(g - o)]
+    bound = [rel * np.linalg.norm(o - b) + abs_rel * np.linalg.norm(o)]
+    if g.ndim == 2:
+        err += list(np.linalg.norm(g - o, axis=1))
+        bound += list(rel * np.linalg.norm(o - b, axis=1) + abs_rel * np.linalg.norm(o, axis=1))
+    err, bound = np.array(err), np.array(bound)
+    over = np.where(bound > 0, err / np.where(bound > 0, bound, 1.0), np.where(err > 0, np.inf, 0.0))
+    k = int(np.argmax(over))
+    return bool(np.all(err <= bound)), float(err[k]), float(bound[k])
 
 
 def bf16_scale(A, B, coords):

@@ -180,3 +180,45 @@ def test_relaxed_plan_deals_long_rows():
             np.testing.assert_array_equal(vals2[s:s + L], vals[s:s + L][order])
             np.testing.assert_array_equal(idx2[:, s:s + L], idx[:, s:s + L][:, order])
     assert dealt_rows > 0
+
+
+def test_query_sizes_and_upload_refusals():
+    """ft_plan_query: the plan's device arrays and the per-parameter-set scratch, known before upload;
+    ft_plan_upload refuses a missing, short or misaligned workspace before it copies anything."""
+    dims = [40, 30, 20]
+    c, _ = synth.coords(dims, 6000, 1.2, seed=8)
+    v = np.ones(c.shape[1], dtype=np.float32)
+    J = R = 8
+    plan = _plan(dims, J, R, c, v, chunk=16, head=40)
+    nnz, N = c.shape[1], 3
+    # every mode holds at least its row pointers, N - 1 index columns, values, segments and segment
+    # pointers; the scratch at least the J x R partial sums of 2048 workgroups and the FP64 loss partials
+    floor = sum(2 * (d + 1) * 8 + (N - 1) * nnz * 4 + nnz * 4 + plan.mode_info(m)["segments"] * 16
+                for m, d in enumerate(dims))
+    assert plan.device_bytes >= floor
+    assert plan.scratch_bytes >= 2048 * J * R * 4 + 2048 * 8
+    # sharing g per fiber adds the fiber arrays to the plan and the g table to the scratch
+    shared = [m for m in range(3) if plan.mode_info(m)["fiber_shared"]]
+    assert shared
+    off = _plan(dims, J, R, c, v, chunk=16, head=40, fiber_share=False)
+    assert plan.device_bytes - off.device_bytes >= sum(nnz * 4 for _ in shared)
+    assert plan.scratch_bytes > off.scratch_bytes
+    lib = _lib.load()
+    fake = 1 << 20  # an aligned address the library must not touch: every case below fails before a copy
+    for ptr, nbytes in ((None, plan.device_bytes), (fake, plan.device_bytes - 1), (fake + 8, plan.device_bytes)):
+        assert lib.ft_plan_upload(plan.handle, ptr, nbytes, None) == 8  # FT_ERR_WORKSPACE
+    assert lib.ft_plan_upload(None, fake, plan.device_bytes, None) == 1  # FT_ERR_ARG
+
+
+def test_refuses_dims_beyond_32bit_gather_offsets():
+    """C rows are gathered by 32-bit byte offsets: I_n * R * 4 must stay below 2^31 (FT_ERR_SHAPE)."""
+    R = 32
+    lim = (1 << 31) // (4 * R)
+    c = np.zeros((3, 4), dtype=np.int32)
+    v = np.ones(4, dtype=np.float32)
+    for dims in ([lim, 5, 5], [5, 5, lim]):
+        with pytest.raises(ft.FtError) as e:
+            _plan(dims, R, R, c, v)
+        assert e.value.status == 2
+    ok = _plan([lim - 1, 5, 5], R, R, c, v)
+    assert ok.mode_info(0)["rows"] == lim - 1
