@@ -190,11 +190,13 @@ ft_status ft_plan_mode_info(const ft_plan* plan, int32_t mode, ft_mode_info* inf
  *   row_ptr int64[I_m + 1]; idx int32[(N-1) * nnz] where column k holds the
  *   indices of mode (m + 1 + k) mod N; vals float[nnz]; perm int64[nnz]
  *   maps a CSR position to the element's input position.  Any may be NULL.
- *   Rows are sorted by (i_m, i_{m+1}, ..., i_{m-1}); with FT_RELAXED the rows
- *   longer than the head hold their elements in the dealt (stride) order.
+ *   Rows are sorted by (i_m, i_{m+1}, ..., i_{m-1}).  factor_order != 0
+ *   returns the order the factor passes read instead: with FT_RELAXED, rows
+ *   longer than the head hold their elements in the dealt (stride) order
+ *   there; otherwise it is the sorted order.
  */
-ft_status ft_plan_host_csr(const ft_plan* plan, int32_t mode, int64_t* row_ptr, int32_t* idx, float* vals,
-                           int64_t* perm);
+ft_status ft_plan_host_csr(const ft_plan* plan, int32_t mode, int32_t factor_order, int64_t* row_ptr, int32_t* idx,
+                           float* vals, int64_t* perm);
 
 /*
  * ft_refresh -- C(n) = A(n) B(n) for n = mode, or for every mode if mode < 0

@@ -131,7 +131,7 @@ def load():
         "ft_plan_upload": ([vp, vp, ctypes.c_size_t, vp], i32),
         "ft_plan_destroy": ([vp], None),
         "ft_plan_mode_info": ([vp, i32, P(FtModeInfo)], i32),
-        "ft_plan_host_csr": ([vp, i32, vp, vp, vp, vp], i32),
+        "ft_plan_host_csr": ([vp, i32, i32, vp, vp, vp, vp], i32),
         "ft_refresh": ([vp, P(FtParams), i32, vp], i32),
         "ft_predict": ([vp, P(FtParams), vp, i64, vp, vp], i32),
         "ft_factor_pass": ([vp, P(FtParams), i32, dbl, dbl, vp], i32),

@@ -97,15 +97,16 @@ class Plan:
         check(self._lib.ft_plan_mode_info(self._h, int(m), ctypes.byref(info)))
         return {k: getattr(info, k) for k, _ in FtModeInfo._fields_}
 
-    def host_csr(self, m: int):
-        """(row_ptr, idx [(N-1), nnz], vals, perm) of mode m (plan built with keep_host=True)."""
+    def host_csr(self, m: int, factor_order: bool = False):
+        """(row_ptr, idx [(N-1), nnz], vals, perm) of mode m (plan built with keep_host=True); with factor_order,
+        in the order the factor passes read (long rows dealt under relaxed=True)."""
         I = self.dims[m]
         row_ptr = np.empty(I + 1, dtype=np.int64)
         idx = np.empty((self.order - 1, self.nnz), dtype=np.int32)
         vals = np.empty(self.nnz, dtype=np.float32)
         perm = np.empty(self.nnz, dtype=np.int64)
-        check(self._lib.ft_plan_host_csr(self._h, int(m), row_ptr.ctypes.data, idx.ctypes.data, vals.ctypes.data,
-                                         perm.ctypes.data))
+        check(self._lib.ft_plan_host_csr(self._h, int(m), 1 if factor_order else 0, row_ptr.ctypes.data,
+                                         idx.ctypes.data, vals.ctypes.data, perm.ctypes.data))
         return row_ptr, idx, vals, perm
 
     def profile(self, enable: bool = True):

@@ -688,17 +688,19 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, const Scra
   if constexpr (!NC) {
     if (P->relaxed) {
       // short rows and heads (in place), then the chunks from the rows as their heads left them, then the
-      // two merge levels
+      // two merge levels; long rows are read in their dealt order
+      const int32_t* fidx = D.fidx ? D.fidx : D.idx;
+      const float* fval = D.fval ? D.fval : D.val;
       if (M.n_apply > 0) {
         KTimer tm(P, FT_K_FACTOR_APPLY, s);
         hipLaunchKernelGGL((k_factor_apply<N, J, R, T, FIB>), dim3(factor_blocks(nullptr, M.n_apply)), dim3(256), 0,
-                           s, D.apply, M.n_apply, D.idx, P->nnz, D.val, cp, Bm, p->A[m], nullptr, flr, c1, D.fid,
+                           s, D.apply, M.n_apply, fidx, P->nnz, fval, cp, Bm, p->A[m], nullptr, flr, c1, D.fid,
                            S.gfib, nc, S.maps, D.row_ptr, rho);
       }
       if (M.n_compose > 0) {
         KTimer tm(P, FT_K_FACTOR_COMPOSE, s);
         hipLaunchKernelGGL((k_factor_apply<N, J, R, T, FIB, false, true>), dim3(factor_blocks(nullptr, M.n_compose)),
-                           dim3(256), 0, s, D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm, p->A[m], S.hvec,
+                           dim3(256), 0, s, D.compose, M.n_compose, fidx, P->nnz, fval, cp, Bm, p->A[m], S.hvec,
                            flr, c1, D.fid, S.gfib, nc, S.maps, D.row_ptr, rho);
       }
       if (M.n_relax > 0) {

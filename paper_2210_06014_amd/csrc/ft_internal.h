@@ -60,6 +60,11 @@ struct ModeHost {
   std::vector<int64_t> seg_ptr;   // I+1: segments of row i are seg_ptr[i]..seg_ptr[i+1]-1
   std::vector<int32_t> fid;       // nnz: fiber of the element at each CSR position
   std::vector<int32_t> fib_idx;   // (N-1) x fibers: fixed indices of each fiber (modes m+1, ..., m-1)
+  // FT_RELAXED with rows longer than the head: idx, val and perm with those
+  // rows dealt in stride order (the order of the factor passes); empty otherwise
+  std::vector<int32_t> fidx;
+  std::vector<float> fval;
+  std::vector<int64_t> fperm;     // host only (ft_plan_host_csr)
 };
 
 struct ModeDev {
@@ -75,12 +80,14 @@ struct ModeDev {
   int64_t* seg_ptr = nullptr;
   int32_t* fid = nullptr;
   int32_t* fib_idx = nullptr;
+  int32_t* fidx = nullptr;  // factor-order copies (FT_RELAXED), or null: the factor passes read idx, val
+  float* fval = nullptr;
 };
 
 // Byte offsets of a mode's arrays in the caller's plan workspace (SIZE_MAX:
 // the array is empty and its device pointer stays null).
 struct ModeOff {
-  size_t row_ptr, idx, val, perm, compose, apply, levels, relax, segs, seg_ptr, fid, fib_idx;
+  size_t row_ptr, idx, val, perm, compose, apply, levels, relax, segs, seg_ptr, fid, fib_idx, fidx, fval;
 };
 
 // Every array in a device workspace starts on this boundary.

@@ -170,34 +170,43 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   // (Q = ceil(L / head): positions 0, Q, 2Q, ..., then 1, 1 + Q, ...) so that
   // its head and each chunk hold a sample of the whole row rather than a
   // narrow slice of the sorted order.  Only the factor passes depend on the
-  // order within a row; the segment sums of the other passes do not.
+  // order within a row, so they read a dealt copy of the indices and values
+  // (fidx, fval) and the fiber ids (read by nothing else) are dealt in place;
+  // the core, loss and gradient passes keep the sorted arrays, whose
+  // neighbouring elements share the next mode's index (cache locality of the
+  // gathers).
   if (P->relaxed && P->head > 0) {
     const int64_t hl0 = P->head;
     int64_t maxL = 0;
     for (int64_t i = 0; i < I; ++i) maxL = std::max(maxL, H.row_ptr[i + 1] - H.row_ptr[i]);
-    try {
-      std::vector<int64_t> src((size_t)std::max<int64_t>(maxL, 1));
-      std::vector<int32_t> t32((size_t)std::max<int64_t>(maxL, 1));
-      std::vector<int64_t> t64((size_t)std::max<int64_t>(maxL, 1));
-      std::vector<float> tf((size_t)std::max<int64_t>(maxL, 1));
-      auto deal = [&](auto* base, auto& tmp, int64_t s, int64_t L) {
-        for (int64_t t = 0; t < L; ++t) tmp[t] = base[s + src[t]];
-        for (int64_t t = 0; t < L; ++t) base[s + t] = tmp[t];
-      };
-      for (int64_t i = 0; i < I; ++i) {
-        const int64_t s = H.row_ptr[i], L = H.row_ptr[i + 1] - s;
-        if (L <= hl0) continue;
-        const int64_t Q = (L + hl0 - 1) / hl0;
-        int64_t o = 0;
-        for (int64_t r = 0; r < Q; ++r)
-          for (int64_t t = r; t < L; t += Q) src[o++] = t;
-        for (int k = 0; k < N - 1; ++k) deal(H.idx.data() + (int64_t)k * nnz, t32, s, L);
-        deal(H.val.data(), tf, s, L);
-        deal(H.perm.data(), t64, s, L);
-        if (!H.fid.empty()) deal(H.fid.data(), t32, s, L);
+    if (maxL > hl0) {
+      try {
+        H.fidx = H.idx;
+        H.fval = H.val;
+        H.fperm = H.perm;
+        std::vector<int64_t> src((size_t)maxL);
+        std::vector<int32_t> t32((size_t)maxL);
+        std::vector<int64_t> t64((size_t)maxL);
+        std::vector<float> tf((size_t)maxL);
+        auto deal = [&](auto* base, auto& tmp, int64_t s, int64_t L) {
+          for (int64_t t = 0; t < L; ++t) tmp[t] = base[s + src[t]];
+          for (int64_t t = 0; t < L; ++t) base[s + t] = tmp[t];
+        };
+        for (int64_t i = 0; i < I; ++i) {
+          const int64_t s = H.row_ptr[i], L = H.row_ptr[i + 1] - s;
+          if (L <= hl0) continue;
+          const int64_t Q = (L + hl0 - 1) / hl0;
+          int64_t o = 0;
+          for (int64_t r = 0; r < Q; ++r)
+            for (int64_t t = r; t < L; t += Q) src[o++] = t;
+          for (int k = 0; k < N - 1; ++k) deal(H.fidx.data() + (int64_t)k * nnz, t32, s, L);
+          deal(H.fval.data(), tf, s, L);
+          deal(H.fperm.data(), t64, s, L);
+          if (!H.fid.empty()) deal(H.fid.data(), t32, s, L);
+        }
+      } catch (const std::bad_alloc&) {
+        return fail(FT_ERR_NOMEM, "host allocation failed while dealing mode " + std::to_string(m));
       }
-    } catch (const std::bad_alloc&) {
-      return fail(FT_ERR_NOMEM, "host allocation failed while dealing mode " + std::to_string(m));
     }
   }
 
@@ -377,6 +386,8 @@ static void layout(ft_plan* P) {
     o.segs = L.add(H.segs.size() * sizeof(Seg));
     o.seg_ptr = L.add(H.seg_ptr.size() * sizeof(int64_t));
     o.fid = L.add(M.use_fiber ? H.fid.size() * sizeof(int32_t) : 0);
+    o.fidx = L.add(H.fidx.size() * sizeof(int32_t));
+    o.fval = L.add(H.fval.size() * sizeof(float));
     o.fib_idx = L.add(M.use_fiber ? H.fib_idx.size() * sizeof(int32_t) : 0);
     if (M.use_fiber) max_fib = std::max(max_fib, M.n_fibers);
     max_slots = std::max(max_slots, M.n_maps + M.n_level_out0);
@@ -548,6 +559,8 @@ extern "C" ft_status ft_plan_upload(ft_plan* P, void* ws, size_t ws_bytes, void*
     if (e == hipSuccess) e = copy_in(ws, o.seg_ptr, H.seg_ptr, s);
     if (e == hipSuccess) e = copy_in(ws, o.fid, H.fid, s);
     if (e == hipSuccess) e = copy_in(ws, o.fib_idx, H.fib_idx, s);
+    if (e == hipSuccess) e = copy_in(ws, o.fidx, H.fidx, s);
+    if (e == hipSuccess) e = copy_in(ws, o.fval, H.fval, s);
   }
   const hipError_t w = hipStreamSynchronize(s);
   if (e == hipSuccess) e = w;
@@ -567,6 +580,8 @@ extern "C" ft_status ft_plan_upload(ft_plan* P, void* ws, size_t ws_bytes, void*
     D.seg_ptr = at<int64_t>(ws, o.seg_ptr);
     D.fid = at<int32_t>(ws, o.fid);
     D.fib_idx = at<int32_t>(ws, o.fib_idx);
+    D.fidx = at<int32_t>(ws, o.fidx);
+    D.fval = at<float>(ws, o.fval);
   }
   P->uploaded = true;
   if (!(P->desc.flags & FT_KEEP_HOST)) {
@@ -585,15 +600,19 @@ extern "C" ft_status ft_plan_mode_info(const ft_plan* P, int32_t mode, ft_mode_i
   return FT_OK;
 }
 
-extern "C" ft_status ft_plan_host_csr(const ft_plan* P, int32_t mode, int64_t* row_ptr, int32_t* idx, float* vals,
-                                      int64_t* perm) {
+extern "C" ft_status ft_plan_host_csr(const ft_plan* P, int32_t mode, int32_t factor_order, int64_t* row_ptr,
+                                      int32_t* idx, float* vals, int64_t* perm) {
   if (!P) return fail(FT_ERR_ARG, "null plan");
   if (mode < 0 || mode >= P->N) return fail(FT_ERR_ARG, "mode out of range");
   if (!P->host_valid) return fail(FT_ERR_STATE, "host plan not kept (use FT_KEEP_HOST)");
   const ModeHost& H = P->host[mode];
+  const bool dealt = factor_order && !H.fidx.empty();
+  const std::vector<int32_t>& I = dealt ? H.fidx : H.idx;
+  const std::vector<float>& V = dealt ? H.fval : H.val;
+  const std::vector<int64_t>& Pm = dealt ? H.fperm : H.perm;
   if (row_ptr) std::memcpy(row_ptr, H.row_ptr.data(), H.row_ptr.size() * sizeof(int64_t));
-  if (idx && !H.idx.empty()) std::memcpy(idx, H.idx.data(), H.idx.size() * sizeof(int32_t));
-  if (vals && !H.val.empty()) std::memcpy(vals, H.val.data(), H.val.size() * sizeof(float));
-  if (perm && !H.perm.empty()) std::memcpy(perm, H.perm.data(), H.perm.size() * sizeof(int64_t));
+  if (idx && !I.empty()) std::memcpy(idx, I.data(), I.size() * sizeof(int32_t));
+  if (vals && !V.empty()) std::memcpy(vals, V.data(), V.size() * sizeof(float));
+  if (perm && !Pm.empty()) std::memcpy(perm, Pm.data(), Pm.size() * sizeof(int64_t));
   return FT_OK;
 }

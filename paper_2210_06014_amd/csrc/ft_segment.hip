@@ -554,6 +554,8 @@ hipError_t segsum_impl(const ft_plan* P, int m, const ft_params* p, float* parti
   return hipGetLastError();
 }
 
+// dpart: kPartials FP64 partials of the loss kernel, then 2 N kSumsqBlocks of
+// the regularisers.
 template <int N, int J, int R, class T>
 hipError_t loss_impl(const ft_plan* P, const ft_params* p, double* dpart, double lam_a, double lam_b, double* out4,
                      float* xout, hipStream_t s) {
