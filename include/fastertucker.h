@@ -16,7 +16,9 @@
  *    buffer: the plan's arrays live in a workspace the caller hands to
  *    ft_plan_upload (size from ft_plan_query), and each parameter set brings
  *    its own scratch buffer (ft_params.scratch, size from ft_plan_query).
- *    Both must be 256-byte aligned (torch allocations are).
+ *    Both must be 256-byte aligned (torch allocations are).  The one device
+ *    array of the library itself is the fixed 56 KiB static scratch of
+ *    ft_loss_noalloc.
  *  - Matrices are dense row-major FP32 in device memory owned by the caller
  *    (A(n): I_n x J, B(n): J x R, C(n): I_n x R).  Eq. (1) allows a J_n per
  *    mode; the kernels are compiled for one J shared by all modes, so every
@@ -259,6 +261,24 @@ ft_status ft_epoch(const ft_plan* plan, const ft_params* p, double lr_a, double 
  */
 ft_status ft_loss(const ft_plan* plan, const ft_params* p, double lam_a, double lam_b, double* d_out4,
                   void* stream);
+
+/*
+ * ft_loss_noalloc -- ft_loss for callers that cannot allocate device memory
+ * or bring a scratch buffer: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Same kernels, launch grid and
+ * result as ft_loss (bit for bit); ft_params.scratch may be NULL.  The FP64
+ * partial sums live in a static device array of the library (56 KiB:
+ * 2048 loss partials plus 2 FT_MAX_ORDER x 256 regulariser partials), held on
+ * every GPU the library runs on until the process ends and located on the
+ * first call on each device (make that first call outside graph capture).
+ * Nothing is allocated, freed or memset; kernel timing (ft_profile_enable) is
+ * skipped for this call.  Every call on a GPU shares that GPU's array, so
+ * calls that overlap on one GPU (two streams, two threads) race and give
+ * wrong sums; serialise them.  A plan needing more partials than the array
+ * holds gets FT_ERR_WORKSPACE (no plan of order <= FT_MAX_ORDER does).
+ */
+ft_status ft_loss_noalloc(const ft_plan* plan, const ft_params* p, double lam_a, double lam_b, double* d_out4,
+                          void* stream);
 
 /* ft_forward -- xhat of every element of the plan, in input order, into
  * d_out float[nnz].  Needs FT_WITH_PERM. */

@@ -17,6 +17,7 @@ from .api import (  # noqa: F401
     forward,
     grad,
     loss,
+    loss_noalloc,
     predict,
     refresh,
     supported,

@@ -43,6 +43,7 @@ SYMBOLS = [
     "ft_core_epoch",
     "ft_epoch",
     "ft_loss",
+    "ft_loss_noalloc",
     "ft_forward",
     "ft_grad",
     "ft_profile_enable",
@@ -141,6 +142,7 @@ def load():
         "ft_core_epoch": ([vp, P(FtParams), dbl, dbl, vp], i32),
         "ft_epoch": ([vp, P(FtParams), dbl, dbl, dbl, dbl, vp], i32),
         "ft_loss": ([vp, P(FtParams), dbl, dbl, vp, vp], i32),
+        "ft_loss_noalloc": ([vp, P(FtParams), dbl, dbl, vp, vp], i32),
         "ft_forward": ([vp, P(FtParams), vp, vp], i32),
         "ft_grad": ([vp, P(FtParams), vp, vp, vp, vp], i32),
         "ft_profile_enable": ([vp, i32], i32),

@@ -198,10 +198,11 @@ class Params:
                 want(self.B16[n], f"B16[{n}]", (J, R), torch.bfloat16)
                 want(self.C16[n], f"C16[{n}]", (I, R), torch.bfloat16)
 
-    def struct(self, plan: "Plan") -> FtParams:
-        """The ft_params of this set for calls with `plan` (validated; scratch sized for the plan)."""
+    def struct(self, plan: "Plan", with_scratch: bool = True) -> FtParams:
+        """The ft_params of this set for calls with `plan` (validated; scratch sized for the plan, or none with
+        with_scratch=False for the entry points that use no caller scratch)."""
         self.check(plan)
-        scratch = self.ensure_scratch(plan.scratch_bytes)
+        scratch = self.ensure_scratch(plan.scratch_bytes) if with_scratch else None
         s = FtParams()
         s.storage = _lib.FT_STORE_BF16 if self.storage == "bf16" else _lib.FT_STORE_F32
         for n in range(len(self.A)):
@@ -213,8 +214,8 @@ class Params:
                 s.A16[n] = self.A16[n].data_ptr()
                 s.B16[n] = self.B16[n].data_ptr()
                 s.C16[n] = self.C16[n].data_ptr()
-        s.scratch = scratch.data_ptr()
-        s.scratch_bytes = scratch.numel()
+        s.scratch = scratch.data_ptr() if scratch is not None else None
+        s.scratch_bytes = scratch.numel() if scratch is not None else 0
         return s
 
     def clone(self) -> "Params":
@@ -307,6 +308,23 @@ def loss(plan: Plan, params: Params, lam_a: float = 0.0, lam_b: float = 0.0, out
         out = torch.empty(4, dtype=torch.float64, device=params.A[0].device)
     _device_vector(out, "out", 4, torch.float64)
     check(plan._lib.ft_loss(plan.handle, _p(plan, params), float(lam_a), float(lam_b), out.data_ptr(), _stream()))
+    return out
+
+
+def loss_noalloc(plan: Plan, params: Params, lam_a: float = 0.0, lam_b: float = 0.0, out=None):
+    """As loss(), through ft_loss_noalloc: no scratch from the caller, nothing allocated by the library (the
+    partial sums live in its static device array).  `out` (float64 CUDA tensor of 4) is written in place;
+    give one to keep this call free of torch allocations too."""
+    import torch
+
+    if out is None:
+        out = torch.empty(4, dtype=torch.float64, device=params.A[0].device)
+    _device_vector(out, "out", 4, torch.float64)
+    if plan.workspace is None:
+        raise RuntimeError("plan not uploaded")
+    s = params.struct(plan, with_scratch=False)
+    check(plan._lib.ft_loss_noalloc(plan.handle, ctypes.byref(s), float(lam_a), float(lam_b), out.data_ptr(),
+                                    _stream()))
     return out
 
 

@@ -176,6 +176,18 @@ extern "C" ft_status ft_loss(const ft_plan* P, const ft_params* p, double lam_a,
   return hip_status(launch_loss(P, p, scratch_of(P, p), lam_a, lam_b, d_out4, (hipStream_t)stream), "loss");
 }
 
+extern "C" ft_status ft_loss_noalloc(const ft_plan* P, const ft_params* p, double lam_a, double lam_b,
+                                     double* d_out4, void* stream) {
+  FT_TRY(check_plan(P));
+  FT_TRY(check_params(P, p));
+  if (!d_out4) return fail(FT_ERR_ARG, "null output");
+  if (noalloc_loss_need(P) > noalloc_loss_capacity())
+    return fail(FT_ERR_WORKSPACE, "ft_loss_noalloc needs " + std::to_string(noalloc_loss_need(P)) +
+                                      " bytes of static scratch, the library holds " +
+                                      std::to_string(noalloc_loss_capacity()));
+  return hip_status(launch_loss_noalloc(P, p, lam_a, lam_b, d_out4, (hipStream_t)stream), "loss (no allocation)");
+}
+
 extern "C" ft_status ft_forward(const ft_plan* P, const ft_params* p, float* d_out, void* stream) {
   FT_TRY(check_plan(P));
   FT_TRY(check_params(P, p));

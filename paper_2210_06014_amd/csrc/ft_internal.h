@@ -188,6 +188,18 @@ constexpr int kRelaxGroup = 256; // chunks per level-1 group of the relaxed merg
 // (8-byte aligned) J + 1 doubles per level-1 group
 inline int64_t relax_incr_floats(int64_t n_maps, int J) { return (n_maps * (J + 1) + 1) / 2 * 2; }
 
+// Launches on this thread inside an UntimedScope create no timing events
+// (the entry point that must not allocate).
+inline bool& untimed_flag() {
+  static thread_local bool f = false;
+  return f;
+}
+struct UntimedScope {
+  bool prev;
+  UntimedScope() : prev(untimed_flag()) { untimed_flag() = true; }
+  ~UntimedScope() { untimed_flag() = prev; }
+};
+
 // Brackets one kernel launch with events when timing is enabled on the plan.
 struct KTimer {
   const ft_plan* P;
@@ -195,7 +207,7 @@ struct KTimer {
   hipStream_t s;
   hipEvent_t a = nullptr;
   KTimer(const ft_plan* P_, int kid_, hipStream_t s_) : P(P_), kid(kid_), s(s_) {
-    if (P && P->prof_on && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+    if (P && P->prof_on && !untimed_flag() && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
   }
   ~KTimer() {
     if (!a) return;
@@ -225,6 +237,12 @@ hipError_t launch_loss(const ft_plan* P, const ft_params* p, const Scratch& S, d
                        double* out4, hipStream_t s);
 hipError_t launch_predict(const ft_plan* P, const ft_params* p, const int32_t* coords, int64_t q, float* out,
                           hipStream_t s);
+// ft_loss_noalloc: the loss with its partials in the library's static device
+// array (capacity and the bytes a plan needs, in bytes)
+size_t noalloc_loss_capacity();
+size_t noalloc_loss_need(const ft_plan* P);
+hipError_t launch_loss_noalloc(const ft_plan* P, const ft_params* p, double lam_a, double lam_b, double* out4,
+                               hipStream_t s);
 hipError_t launch_forward(const ft_plan* P, const ft_params* p, const Scratch& S, float* out, hipStream_t s);
 hipError_t launch_grad(const ft_plan* P, const ft_params* p, const Scratch& S, const float* upstream,
                        float* const* gA, float* const* gB, hipStream_t s);

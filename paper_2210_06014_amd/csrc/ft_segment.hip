@@ -1,4 +1,6 @@
 // Segment passes: core gradient, loss, forward, gradient, predict.
+#include <mutex>
+
 #include "ft_device.h"
 
 namespace ft {
@@ -704,6 +706,57 @@ hipError_t launch_grad(const ft_plan* P, const ft_params* p, const Scratch& S, c
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// Scratch of ft_loss_noalloc: the FP64 partials of the loss kernel (at most
+// kPartials workgroups) followed by those of the regulariser sums
+// (2 N kSumsqBlocks), in a device array that the library holds on every GPU
+// it runs on until the process ends.  Host code uses the address looked up
+// per device below, never the array's name.
+constexpr size_t kNoAllocDoubles = (size_t)kPartials + 2 * FT_MAX_ORDER * kSumsqBlocks;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+size_t noalloc_loss_capacity() { return sizeof(double) * kNoAllocDoubles; }
+
+size_t noalloc_loss_need(const ft_plan* P) {
+  return sizeof(double) * ((size_t)kPartials + 2 * (size_t)P->N * kSumsqBlocks);
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device: looked up on the first
+// call on each device (with that device current) and kept.
+hipError_t noalloc_scratch(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* addr = nullptr;
+    e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!addr) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[dev] = static_cast<double*>(addr);
+  }
+  *out = g_noalloc_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_loss_noalloc(const ft_plan* P, const ft_params* p, double lam_a, double lam_b, double* out4,
+                               hipStream_t s) {
+  double* d = nullptr;
+  hipError_t e = noalloc_scratch(&d);
+  if (e != hipSuccess) return e;
+  Scratch S{};
+  S.dpartials = d;
+  // kernel timing creates events; this path creates nothing
+  const UntimedScope untimed;
+  return launch_loss(P, p, S, lam_a, lam_b, out4, s);
 }
 
 }  // namespace ft
