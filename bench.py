@@ -53,7 +53,8 @@ def algorithmic(w, nnz, row_counts, head, fibers, relaxed=False, sp=4):
     N, J, R = len(w.dims), w.J[0], w.R
     stream = (N - 1) * 4 + 4
     out = {"factor_compose": [0.0, 0.0], "factor_apply": [0.0, 0.0], "fiber_g": [0.0, 0.0], "segsum": [0.0, 0.0],
-           "loss": [0.0, 0.0], "compose_executed": [0.0, 0.0]}
+           "loss": [0.0, 0.0], "compose_executed": [0.0, 0.0], "factor_fused": [0.0, 0.0],
+           "fused_executed": [0.0, 0.0]}
     c_bytes = [d * R * sp for d in w.dims]
     a_bytes = [d * J * 4 for d in w.dims]
     a_read = [d * J * sp for d in w.dims]
@@ -87,6 +88,10 @@ def algorithmic(w, nnz, row_counts, head, fibers, relaxed=False, sp=4):
         out["segsum"][1] += nnz * stream + others + c_bytes[m] + a_read[m]
     out["loss"][0] += nnz * (N * R + 3)
     out["loss"][1] += nnz * stream + sum(c_bytes)
+    # the exact passes launch the in-place items and the chunk maps as one kernel
+    for k in (0, 1):
+        out["factor_fused"][k] = out["factor_compose"][k] + out["factor_apply"][k]
+    out["fused_executed"][0] = out["compose_executed"][0] + out["factor_apply"][0]
     return out
 
 
@@ -285,14 +290,15 @@ def rooflines(w, nnz, c, plan, prof, steps, storage, head, relaxed, counters_ok)
         flops, byts = alg.get(k, [0.0, 0.0])
         launches = kernels[k]["launches_per_step"]
         traffic = counter_traffic(w.name, storage, k) if counters_ok else None
-        if k in ("factor_compose", "factor_apply"):
+        if k in ("factor_compose", "factor_apply", "factor_fused"):
             ach = flops / t_s / 1e12
             r = {"kernel": k, "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                  "frac": ach / PEAK_FP32_TFLOPS, "traffic": traffic, "algorithmic_per_launch": flops / launches,
                  "algorithmic_bytes_per_launch": byts / launches, "avg_launch_us": kernels[k]["avg_launch_us"]}
-            if k == "factor_compose":
-                ex = alg["compose_executed"][0] / t_s / 1e12
-                r.update({"executed_per_launch": alg["compose_executed"][0] / launches, "executed_achieved": ex,
+            if k in ("factor_compose", "factor_fused"):
+                exk = "compose_executed" if k == "factor_compose" else "fused_executed"
+                ex = alg[exk][0] / t_s / 1e12
+                r.update({"executed_per_launch": alg[exk][0] / launches, "executed_achieved": ex,
                           "executed_frac": ex / PEAK_FP32_TFLOPS})
             return r
         ach = byts / t_s / 1e9
@@ -306,7 +312,7 @@ def rooflines(w, nnz, c, plan, prof, steps, storage, head, relaxed, counters_ok)
         if "segsum" in kernels:
             gather = obj("segsum")
     for k in kernels:
-        if k in alg and k != "compose_executed":
+        if k in alg and k not in ("compose_executed", "fused_executed"):
             t_k = kernels[k]["ms_per_step"] / 1e3
             kernels[k]["alg_tflops"] = alg[k][0] / t_k / 1e12
             kernels[k]["alg_gbs"] = alg[k][1] / t_k / 1e9
@@ -319,9 +325,9 @@ def leg(ft, w, c, plan, A, B, storage, args, nnz, relaxed=False):
     ft.refresh(plan, prm)
     ms, prof, rmse0, rmse = time_steps(ft, plan, prm, w, args.steps, args.warmup, not args.no_profile)
     log(f"{w.name} {storage}: {ms:.3f} ms/step, RMSE {rmse0:.7f} -> {rmse:.7f}")
-    head = args.head or 2 * (args.chunk or 512)
+    head = plan.mode_info(0)["head"]
     counters_ok = (args.nnz is None and not args.chunk and not args.head and not args.no_fiber_share
-                   and not args.no_c_cache and not relaxed)
+                   and not args.no_c_cache and not relaxed and not args.split_factor)
     kernels, dom, gather, infos, fibers = rooflines(w, nnz, c, plan, prof, args.steps, storage, head, relaxed,
                                                     counters_ok)
     passes = time_passes(ft, plan, prm, w, args.steps)
@@ -396,6 +402,9 @@ def main():
                     help="form g = B(m) w per element instead of once per mode-m fiber (Section 3.2 ablation)")
     ap.add_argument("--no-c-cache", action="store_true",
                     help="factor and core passes form C rows from A and B on use (FastTucker's cost; Table 5 ablation)")
+    ap.add_argument("--split-factor", action="store_true",
+                    help="launch the in-place items and the chunk maps of the exact factor passes as two kernels "
+                    "(FT_SPLIT_FACTOR; the layout before fusing them)")
     ap.add_argument("--relaxed", action="store_true",
                     help="relaxed factor passes: chunks of long rows start from the row as its head left it and "
                     "their increments are merged with a step guard (FT_RELAXED)")
@@ -441,7 +450,7 @@ def main():
     log(f"generated in {time.time() - t:.1f} s")
     t = time.time()
     plan = ft.Plan(w.dims, J, R, c, v, chunk=args.chunk, head=args.head, fiber_share=not args.no_fiber_share,
-                   c_cache=not args.no_c_cache, relaxed=args.relaxed)
+                   c_cache=not args.no_c_cache, relaxed=args.relaxed, fused=not args.split_factor)
     log(f"plan built and uploaded in {time.time() - t:.1f} s ({plan.device_bytes / 2**30:.2f} GiB plan, "
         f"{plan.scratch_bytes / 2**20:.1f} MiB scratch per parameter set)")
 

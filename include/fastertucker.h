@@ -85,6 +85,9 @@ typedef enum {
                                order in lr); deterministic.  Rows of at most `head` elements are updated
                                exactly as without the flag.  Not with FT_NO_C_CACHE (FT_ERR_UNSUPPORTED) */
 
+#define FT_SPLIT_FACTOR 32   /* launch the in-place items and the chunk maps of an exact factor pass as two
+                               kernels in sequence instead of one (for comparison; same results) */
+
 /* Shape of the problem and of the plan. */
 typedef struct {
   int32_t order;                /* N, 2..FT_MAX_ORDER */
@@ -99,7 +102,8 @@ typedef struct {
   int32_t fanin;                /* chunk maps folded per combine step (0 or above the maximum: 16 for
                                    J <= 16, 8 above); a row with at most fanin maps has them applied in
                                    sequence to its head's result */
-  int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM | FT_NO_FIBER_SHARE | FT_NO_C_CACHE | FT_RELAXED */
+  int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM | FT_NO_FIBER_SHARE | FT_NO_C_CACHE | FT_RELAXED |
+                                   FT_SPLIT_FACTOR */
 } ft_desc;
 
 /* ft_params.storage */
@@ -141,6 +145,8 @@ typedef struct {
   int32_t combine_levels;
   int32_t fiber_shared;  /* 1 if the factor pass shares g per fiber in this mode */
   int64_t fibers;        /* mode-m fibers: distinct (i_n, n != m) */
+  int32_t head;          /* the plan's head length (ft_desc.head, or its default) */
+  int32_t chunk;         /* the plan's chunk length (ft_desc.chunk, or its default) */
 } ft_mode_info;
 
 typedef struct ft_plan ft_plan;
@@ -313,7 +319,8 @@ typedef enum {
   FT_K_REDUCE = 5,         /* partial-sum reduction and B step */
   FT_K_LOSS = 6,           /* loss and forward gather */
   FT_K_FIBER_G = 7,        /* shared g per fiber */
-  FT_K_COUNT = 8
+  FT_K_FACTOR_FUSED = 8,   /* in-place items and chunk maps of an exact factor pass in one launch */
+  FT_K_COUNT = 9
 } ft_kernel_id;
 ft_status ft_profile_enable(ft_plan* plan, int32_t enable);
 ft_status ft_profile_read(ft_plan* plan, double* ms, int64_t* launches);

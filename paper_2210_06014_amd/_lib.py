@@ -13,6 +13,7 @@ FT_WITH_PERM = 2
 FT_NO_FIBER_SHARE = 4
 FT_NO_C_CACHE = 8
 FT_RELAXED = 16
+FT_SPLIT_FACTOR = 32
 
 STATUS = {
     0: "FT_OK",
@@ -98,10 +99,13 @@ class FtModeInfo(ctypes.Structure):
         ("combine_levels", ctypes.c_int32),
         ("fiber_shared", ctypes.c_int32),
         ("fibers", ctypes.c_int64),
+        ("head", ctypes.c_int32),
+        ("chunk", ctypes.c_int32),
     ]
 
 
-KERNELS = ["factor_compose", "factor_apply", "combine", "refresh", "segsum", "reduce", "loss", "fiber_g"]
+KERNELS = ["factor_compose", "factor_apply", "combine", "refresh", "segsum", "reduce", "loss", "fiber_g",
+           "factor_fused"]
 
 
 class FtError(RuntimeError):

@@ -133,14 +133,13 @@ __global__ __launch_bounds__(256) void k_fiber_g(const int32_t* __restrict__ fib
 //     rho^T (a - rho^len a_H),   T = elements of the row after the chunk,
 // and the sum of ||g||^2 over its steps, J + 1 floats per chunk slot.
 template <int N, int J, int R, class T, bool FIB, bool NC = false, bool RLX = false>
-__global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ items, int64_t n_items,
-                                                      const int32_t* __restrict__ idx, int64_t nnz,
-                                                      const float* __restrict__ val, CPtrs<N, T> cp,
-                                                      const T* __restrict__ Bm, float* __restrict__ Am,
-                                                      float* __restrict__ hvec, float lr, float c1,
-                                                      const int32_t* __restrict__ fid, const float* __restrict__ gfib,
-                                                      NoC<N> nc, float* __restrict__ incr,
-                                                      const int64_t* __restrict__ row_ptr, double rho) {
+__device__ __forceinline__ void apply_item(int64_t gid, const FItem* __restrict__ items, int64_t n_items,
+                                           const int32_t* __restrict__ idx, int64_t nnz, const float* __restrict__ val,
+                                           const CPtrs<N, T>& cp, const T* __restrict__ Bm, float* __restrict__ Am,
+                                           float* __restrict__ hvec, float lr, float c1,
+                                           const int32_t* __restrict__ fid, const float* __restrict__ gfib,
+                                           const NoC<N>& nc, float* __restrict__ incr,
+                                           const int64_t* __restrict__ row_ptr, double rho) {
   constexpr int E = J >= 16 ? J / 16 : 1;
   constexpr int RE = R >= 16 ? R / 16 : 1;
   const int l = threadIdx.x & 15;
@@ -154,9 +153,6 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
   static_assert(!NC || (J == 16 && R == 16 && !FIB), "the no-C-cache variant is built for J = R = 16");
   float Bc[N > 1 ? N - 1 : 1][16];
   if constexpr (NC) load_nc_cols<N>(nc, l, Bc);
-  // One item per 16-lane group: the four groups of a wavefront take four
-  // consecutive items (similar lengths, the lists are sorted).
-  const int64_t gid = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
   FItem it{0, 0, 0, 0, 0};
   if (gid < n_items) it = items[gid];
   // The row is carried in FP64 registers and rounded to FP32 once when
@@ -301,6 +297,21 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
   }
 }
 
+// One item per 16-lane group: the four groups of a wavefront take four
+// consecutive items (similar lengths, the lists are sorted).
+template <int N, int J, int R, class T, bool FIB, bool NC = false, bool RLX = false>
+__global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ items, int64_t n_items,
+                                                      const int32_t* __restrict__ idx, int64_t nnz,
+                                                      const float* __restrict__ val, CPtrs<N, T> cp,
+                                                      const T* __restrict__ Bm, float* __restrict__ Am,
+                                                      float* __restrict__ hvec, float lr, float c1,
+                                                      const int32_t* __restrict__ fid, const float* __restrict__ gfib,
+                                                      NoC<N> nc, float* __restrict__ incr,
+                                                      const int64_t* __restrict__ row_ptr, double rho) {
+  apply_item<N, J, R, T, FIB, NC, RLX>((int64_t)blockIdx.x * 16 + (threadIdx.x >> 4), items, n_items, idx, nnz, val,
+                                       cp, Bm, Am, hvec, lr, c1, fid, gfib, nc, incr, row_ptr, rho);
+}
+
 // Chunk maps.  With rho = 1 - lr lam and gp = lr / rho, one step is
 //     a <- rho (I - gp g g^T) a + lr x g.
 // A chunk of T steps is the affine map a -> rho^T (I + Nm) a + v with
@@ -308,13 +319,13 @@ __global__ __launch_bounds__(256) void k_factor_apply(const FItem* __restrict__ 
 //     v  <- v + (-lr lam) v + lr (x - v.g) g
 // (v is the state reached from a = 0).  Lane j keeps column j of Nm.
 template <int N, int J, int R, class T, bool FIB, bool NC = false>
-__global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict__ items, int64_t n_items,
-                                                        const int32_t* __restrict__ idx, int64_t nnz,
-                                                        const float* __restrict__ val, CPtrs<N, T> cp,
-                                                        const T* __restrict__ Bm, float* __restrict__ maps,
-                                                        double* __restrict__ map_scale, float lr, float c1, float gp,
-                                                        double rho, const int32_t* __restrict__ fid,
-                                                        const float* __restrict__ gfib, NoC<N> nc) {
+__device__ __forceinline__ void compose_item(int64_t gid, const FItem* __restrict__ items, int64_t n_items,
+                                             const int32_t* __restrict__ idx, int64_t nnz,
+                                             const float* __restrict__ val, const CPtrs<N, T>& cp,
+                                             const T* __restrict__ Bm, float* __restrict__ maps,
+                                             double* __restrict__ map_scale, float lr, float c1, float gp, double rho,
+                                             const int32_t* __restrict__ fid, const float* __restrict__ gfib,
+                                             const NoC<N>& nc) {
   constexpr int E = J >= 16 ? J / 16 : 1;
   constexpr int RE = R >= 16 ? R / 16 : 1;
   constexpr int MS = J * J + J;
@@ -329,9 +340,6 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
   static_assert(!NC || (J == 16 && R == 16 && !FIB), "the no-C-cache variant is built for J = R = 16");
   float Bc[N > 1 ? N - 1 : 1][16];
   if constexpr (NC) load_nc_cols<N>(nc, l, Bc);
-  // One item per 16-lane group: the four groups of a wavefront take four
-  // consecutive items (similar lengths, the lists are sorted).
-  const int64_t gid = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
   FItem it{0, 0, 0, 0, 0};
   if (gid < n_items) it = items[gid];
   float Nc[E][J];
@@ -424,6 +432,43 @@ __global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict_
     }
     if (l == 0) map_scale[it.slot] = pow(rho, (double)it.len);
   }
+}
+
+template <int N, int J, int R, class T, bool FIB, bool NC = false>
+__global__ __launch_bounds__(256) void k_factor_compose(const FItem* __restrict__ items, int64_t n_items,
+                                                        const int32_t* __restrict__ idx, int64_t nnz,
+                                                        const float* __restrict__ val, CPtrs<N, T> cp,
+                                                        const T* __restrict__ Bm, float* __restrict__ maps,
+                                                        double* __restrict__ map_scale, float lr, float c1, float gp,
+                                                        double rho, const int32_t* __restrict__ fid,
+                                                        const float* __restrict__ gfib, NoC<N> nc) {
+  compose_item<N, J, R, T, FIB, NC>((int64_t)blockIdx.x * 16 + (threadIdx.x >> 4), items, n_items, idx, nnz, val, cp,
+                                    Bm, maps, map_scale, lr, c1, gp, rho, fid, gfib, nc);
+}
+
+// The in-place items and the chunk maps of one exact factor pass in one
+// launch.  They are independent (a map starts from the identity, not from
+// its row's head), so the first apply_blocks workgroups take the in-place
+// items, heads of long rows first, and the rest the chunk maps: the long
+// serial heads start at once and run while the maps keep the SIMDs busy,
+// instead of running on an otherwise idle GPU after them.
+template <int N, int J, int R, class T, bool FIB, bool NC = false>
+__global__ __launch_bounds__(256) void k_factor_fused(int64_t apply_blocks, const FItem* __restrict__ apply_items,
+                                                      int64_t n_apply, const FItem* __restrict__ compose_items,
+                                                      int64_t n_compose, const int32_t* __restrict__ idx, int64_t nnz,
+                                                      const float* __restrict__ val, CPtrs<N, T> cp,
+                                                      const T* __restrict__ Bm, float* __restrict__ Am,
+                                                      float* __restrict__ hvec, float* __restrict__ maps,
+                                                      double* __restrict__ map_scale, float lr, float c1, float gp,
+                                                      double rho, const int32_t* __restrict__ fid,
+                                                      const float* __restrict__ gfib, NoC<N> nc) {
+  const int64_t grp = threadIdx.x >> 4;
+  if ((int64_t)blockIdx.x < apply_blocks)
+    apply_item<N, J, R, T, FIB, NC, false>((int64_t)blockIdx.x * 16 + grp, apply_items, n_apply, idx, nnz, val, cp,
+                                           Bm, Am, hvec, lr, c1, fid, gfib, nc, nullptr, nullptr, rho);
+  else
+    compose_item<N, J, R, T, FIB, NC>(((int64_t)blockIdx.x - apply_blocks) * 16 + grp, compose_items, n_compose, idx,
+                                      nnz, val, cp, Bm, maps, map_scale, lr, c1, gp, rho, fid, gfib, nc);
 }
 
 // Fold `count` consecutive maps (earliest first) into one, as a binary tree in
@@ -714,14 +759,20 @@ hipError_t factor_launch(const ft_plan* P, int m, const ft_params* p, const Scra
       return hipGetLastError();
     }
   }
-  if (M.n_compose > 0) {
+  if (M.n_compose > 0 && M.n_apply > 0 && P->fused) {
+    KTimer tm(P, FT_K_FACTOR_FUSED, s);
+    const int64_t ab = (M.n_apply + 15) / 16;
+    hipLaunchKernelGGL((k_factor_fused<N, J, R, T, FIB, NC>), dim3((unsigned)(ab + (M.n_compose + 15) / 16)),
+                       dim3(256), 0, s, ab, D.apply, M.n_apply, D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm,
+                       p->A[m], S.hvec, S.maps, S.map_scale, flr, c1, gp, rho, D.fid, S.gfib, nc);
+  } else if (M.n_compose > 0) {
     KTimer tm(P, FT_K_FACTOR_COMPOSE, s);
     hipLaunchKernelGGL((k_factor_compose<N, J, R, T, FIB, NC>),
                        dim3(factor_blocks((const void*)k_factor_compose<N, J, R, T, FIB, NC>, M.n_compose)), dim3(256),
                        0, s, D.compose, M.n_compose, D.idx, P->nnz, D.val, cp, Bm, S.maps, S.map_scale, flr, c1, gp,
                        rho, D.fid, S.gfib, nc);
   }
-  if (M.n_apply > 0) {
+  if (M.n_apply > 0 && !(M.n_compose > 0 && P->fused)) {
     KTimer tm(P, FT_K_FACTOR_APPLY, s);
     hipLaunchKernelGGL((k_factor_apply<N, J, R, T, FIB, NC>),
                        dim3(factor_blocks((const void*)k_factor_apply<N, J, R, T, FIB, NC>, M.n_apply)), dim3(256), 0,

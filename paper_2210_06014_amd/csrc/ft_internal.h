@@ -159,6 +159,7 @@ struct ft_plan {
   int chunk = 512, head = 1024, fanin = 16;
   bool no_c_cache = false;  // FT_NO_C_CACHE
   bool relaxed = false;     // FT_RELAXED
+  bool fused = true;        // exact factor passes launch in-place items and chunk maps together (not FT_SPLIT_FACTOR)
   std::vector<ft::ModeMeta> meta;
   std::vector<ft::ModeHost> host;
   std::vector<ft::ModeDev> dev;

@@ -358,6 +358,8 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   inf.combine_levels = (int32_t)H.levels.size();
   inf.fibers = M.n_fibers;
   inf.fiber_shared = M.use_fiber ? 1 : 0;
+  inf.head = P->head;
+  inf.chunk = P->chunk;
   return FT_OK;
 }
 
@@ -492,6 +494,7 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
   P->head = d->head ? d->head : 2 * P->chunk;
   P->no_c_cache = (d->flags & FT_NO_C_CACHE) != 0;
   P->relaxed = (d->flags & FT_RELAXED) != 0;
+  P->fused = !(d->flags & FT_SPLIT_FACTOR);
   P->fanin = std::min(d->fanin ? d->fanin : max_fanin(d->J[0]), max_fanin(d->J[0]));
   try {
     P->meta.resize(N);

@@ -236,6 +236,35 @@ def test_fiber_shared_g_is_bitwise_equal(case):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("case", ["zipf3_j16_smallchunk", "zipf3_j32", "zipf4_j8", "zipf8_j8r16"])
+def test_fused_factor_launch_is_bitwise_equal(case):
+    """The exact factor pass launches its in-place items and its chunk maps as one kernel by default; as two
+    kernels in sequence (FT_SPLIT_FACTOR) every item runs the same code, so the results are bit-identical.
+    Also with long heads (rows of up to 4 chunks in place), which move elements from the maps to the chains."""
+    import torch
+
+    import paper_2210_06014_amd as ft
+
+    name, dims, nnz, zipf, J, R, kw = [c for c in CASES if c[0] == case][0]
+    vk = "normal3" if len(dims) == 8 else "int1to5"
+    c, v, A, B = make_problem(dims, nnz, zipf, J, R, seed=19, values=vk)
+    chunk = kw.get("chunk", 512)
+    for head in (0, 4 * chunk):
+        outs = []
+        for fused in (True, False):
+            for storage in ("f32", "bf16"):
+                plan, prm = gpu_setup(dims, J, R, c, v, A, B, storage=storage, fused=fused, **kw,
+                                      **({"head": head} if head else {}))
+                assert sum(plan.mode_info(m)["heavy_rows"] for m in range(len(dims))) > 0
+                ft.epoch(plan, prm, 1e-3, 1e-2, 1e-3, 1e-2)
+                torch.cuda.synchronize()
+                outs.append([t.clone() for t in prm.A + prm.B])
+        for a, b in zip(outs[0], outs[2]):
+            assert torch.equal(a, b), (name, head, "f32")
+        for a, b in zip(outs[1], outs[3]):
+            assert torch.equal(a, b), (name, head, "bf16")
+
+
 @pytest.mark.parametrize("case", ["zipf3_j16", "zipf3_j16_smallchunk"])
 def test_no_c_cache_variant(case):
     """FT_NO_C_CACHE (the FastTucker cost, Table 5): every C row formed from A and B on use; same results."""

@@ -93,15 +93,18 @@ def _params(walk_case, storage):
     return prm
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_forward_and_loss_walk(walk_case, storage):
+def test_forward_and_loss_walk(walk_case):
+    name, dims, J, R, c, v, A, B, exact16, plan, orc, ref = walk_case
+    for storage in _storages(exact16):
+        _forward_and_loss(walk_case, storage)
+
+
+def _forward_and_loss(walk_case, storage):
     import torch
 
     import paper_2210_06014_amd as ft
 
     name, dims, J, R, c, v, A, B, exact16, plan, orc, ref = walk_case
-    if storage not in _storages(exact16):
-        pytest.skip("BF16 is checked on the case with BF16-exact parameters")
     prm = _params(walk_case, storage)
     out = torch.full((plan.nnz,), float("nan"), dtype=torch.float32, device="cuda")
     ft.forward(plan, prm, out=out)
@@ -116,13 +119,16 @@ def test_forward_and_loss_walk(walk_case, storage):
     np.testing.assert_allclose(sse, ref["loss"][0], rtol=1e-5)
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_gradient_rows_and_core_gradient_walk(walk_case, storage):
+def test_gradient_rows_and_core_gradient_walk(walk_case):
+    name, dims, J, R, c, v, A, B, exact16, plan, orc, ref = walk_case
+    for storage in _storages(exact16):
+        _gradient_rows(walk_case, storage)
+
+
+def _gradient_rows(walk_case, storage):
     import paper_2210_06014_amd as ft
 
     name, dims, J, R, c, v, A, B, exact16, plan, orc, ref = walk_case
-    if storage not in _storages(exact16):
-        pytest.skip("BF16 is checked on the case with BF16-exact parameters")
     prm = _params(walk_case, storage)
     gA, gB = ft.grad(plan, prm)
     for m in range(len(dims)):
@@ -142,16 +148,19 @@ def test_gradient_rows_and_core_gradient_walk(walk_case, storage):
         assert np.linalg.norm(G - Gr) <= 1e-4 * np.linalg.norm(Gr), (name, storage, m)
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_core_pass_walk(walk_case, storage):
+def test_core_pass_walk(walk_case):
     """One core pass per mode from the same state, B(m) row by row against the oracle's step."""
+    name, dims, J, R, c, v, A, B, exact16, plan, orc, ref = walk_case
+    for storage in _storages(exact16):
+        _core_pass(walk_case, storage)
+
+
+def _core_pass(walk_case, storage):
     import torch
 
     import paper_2210_06014_amd as ft
 
     name, dims, J, R, c, v, A, B, exact16, plan, orc, ref = walk_case
-    if storage not in _storages(exact16):
-        pytest.skip("BF16 is checked on the case with BF16-exact parameters")
     lr, lam = 1e-3, 1e-2
     for m in range(len(dims)):
         prm = _params(walk_case, storage)
