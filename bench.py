@@ -327,7 +327,7 @@ def leg(ft, w, c, plan, A, B, storage, args, nnz, relaxed=False):
     log(f"{w.name} {storage}: {ms:.3f} ms/step, RMSE {rmse0:.7f} -> {rmse:.7f}")
     head = plan.mode_info(0)["head"]
     counters_ok = (args.nnz is None and not args.chunk and not args.head and not args.no_fiber_share
-                   and not args.no_c_cache and not relaxed and not args.split_factor)
+                   and not args.no_c_cache and not relaxed and not args.split_factor and not args.run_reuse)
     kernels, dom, gather, infos, fibers = rooflines(w, nnz, c, plan, prof, args.steps, storage, head, relaxed,
                                                     counters_ok)
     passes = time_passes(ft, plan, prm, w, args.steps)
@@ -405,6 +405,9 @@ def main():
     ap.add_argument("--split-factor", action="store_true",
                     help="launch the in-place items and the chunk maps of the exact factor passes as two kernels "
                     "(FT_SPLIT_FACTOR; the layout before fusing them)")
+    ap.add_argument("--run-reuse", action="store_true",
+                    help="segment passes gather the C row of mode m + 1 once per run of elements sharing it "
+                    "(FT_RUN_REUSE; fewer gathers, measured slower)")
     ap.add_argument("--relaxed", action="store_true",
                     help="relaxed factor passes: chunks of long rows start from the row as its head left it and "
                     "their increments are merged with a step guard (FT_RELAXED)")
@@ -450,7 +453,8 @@ def main():
     log(f"generated in {time.time() - t:.1f} s")
     t = time.time()
     plan = ft.Plan(w.dims, J, R, c, v, chunk=args.chunk, head=args.head, fiber_share=not args.no_fiber_share,
-                   c_cache=not args.no_c_cache, relaxed=args.relaxed, fused=not args.split_factor)
+                   c_cache=not args.no_c_cache, relaxed=args.relaxed, fused=not args.split_factor,
+                   run_reuse=args.run_reuse)
     log(f"plan built and uploaded in {time.time() - t:.1f} s ({plan.device_bytes / 2**30:.2f} GiB plan, "
         f"{plan.scratch_bytes / 2**20:.1f} MiB scratch per parameter set)")
 

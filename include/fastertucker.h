@@ -87,6 +87,11 @@ typedef enum {
 
 #define FT_SPLIT_FACTOR 32   /* launch the in-place items and the chunk maps of an exact factor pass as two
                                kernels in sequence instead of one (for comparison; same results) */
+#define FT_RUN_REUSE 64      /* segment passes (core, loss, forward, gradient) gather the C row of mode m + 1
+                               once per run of a row's elements that share it, each slot of a wavefront
+                               walking a contiguous piece of the segment, instead of gathering every row for
+                               every element (same sums up to rounding order).  Fewer gathers, but measured
+                               slower on MI355X, so it is off by default; kept for comparison */
 
 /* Shape of the problem and of the plan. */
 typedef struct {
@@ -95,15 +100,17 @@ typedef struct {
   int32_t J[FT_MAX_ORDER];      /* factor rank per mode; must all be equal */
   int32_t R;                    /* core rank */
   int64_t nnz;                  /* |Omega|, 0..2^32-1 */
-  int32_t chunk;                /* elements per chunk map of a long row (0: 512) */
+  int32_t chunk;                /* elements per chunk map of a long row (0: 1024 for J >= 32, else 512;
+                                   512 with FT_RELAXED) */
   int32_t head;                 /* rows of at most this many elements are updated as one serial chain; a
                                    longer row has its first `head` elements updated in place and the rest
-                                   cut into chunks (0: 2 chunk) */
+                                   cut into chunks (0: 16 chunks for J >= 32, 8 for J = 16, else 2;
+                                   2 chunks with FT_RELAXED) */
   int32_t fanin;                /* chunk maps folded per combine step (0 or above the maximum: 16 for
                                    J <= 16, 8 above); a row with at most fanin maps has them applied in
                                    sequence to its head's result */
   int32_t flags;                /* FT_KEEP_HOST | FT_WITH_PERM | FT_NO_FIBER_SHARE | FT_NO_C_CACHE | FT_RELAXED |
-                                   FT_SPLIT_FACTOR */
+                                   FT_SPLIT_FACTOR | FT_RUN_REUSE */
 } ft_desc;
 
 /* ft_params.storage */
@@ -147,6 +154,7 @@ typedef struct {
   int64_t fibers;        /* mode-m fibers: distinct (i_n, n != m) */
   int32_t head;          /* the plan's head length (ft_desc.head, or its default) */
   int32_t chunk;         /* the plan's chunk length (ft_desc.chunk, or its default) */
+  int64_t runs;          /* runs of elements of a row sharing the index of mode m + 1 */
 } ft_mode_info;
 
 typedef struct ft_plan ft_plan;

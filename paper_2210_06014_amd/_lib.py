@@ -14,6 +14,7 @@ FT_NO_FIBER_SHARE = 4
 FT_NO_C_CACHE = 8
 FT_RELAXED = 16
 FT_SPLIT_FACTOR = 32
+FT_RUN_REUSE = 64
 
 STATUS = {
     0: "FT_OK",
@@ -101,6 +102,7 @@ class FtModeInfo(ctypes.Structure):
         ("fibers", ctypes.c_int64),
         ("head", ctypes.c_int32),
         ("chunk", ctypes.c_int32),
+        ("runs", ctypes.c_int64),
     ]
 
 

@@ -43,7 +43,7 @@ class Plan:
     `self.workspace`, a torch tensor of `device_bytes` bytes owned by this object."""
 
     def __init__(self, dims, J, R, coords, vals, chunk=0, fanin=0, keep_host=False, with_perm=False, upload=True,
-                 fiber_share=True, head=0, c_cache=True, relaxed=False, fused=True, device="cuda"):
+                 fiber_share=True, head=0, c_cache=True, relaxed=False, fused=True, run_reuse=False, device="cuda"):
         lib = load()
         coords = np.ascontiguousarray(coords, dtype=np.int32)
         vals = np.ascontiguousarray(vals, dtype=np.float32)
@@ -63,7 +63,8 @@ class Plan:
         d.fanin = int(fanin)
         d.flags = ((_lib.FT_KEEP_HOST if keep_host else 0) | (_lib.FT_WITH_PERM if with_perm else 0)
                    | (0 if fiber_share else _lib.FT_NO_FIBER_SHARE) | (0 if c_cache else _lib.FT_NO_C_CACHE)
-                   | (_lib.FT_RELAXED if relaxed else 0) | (0 if fused else _lib.FT_SPLIT_FACTOR))
+                   | (_lib.FT_RELAXED if relaxed else 0) | (0 if fused else _lib.FT_SPLIT_FACTOR)
+                   | (_lib.FT_RUN_REUSE if run_reuse else 0))
         self.dims = [int(x) for x in dims]
         self.order = order
         self.J = Js[0]

@@ -141,6 +141,7 @@ struct ModeMeta {
   int64_t n_relax_groups = 0;  // FT_RELAXED level-1 items
   int64_t n_relax = 0;         // FT_RELAXED level-2 items (heavy rows)
   int64_t n_fibers = 0;
+  int64_t n_runs = 0;  // runs of equal column-0 index within rows
   bool use_fiber = false;
   ft_mode_info info{};
 };
@@ -160,6 +161,8 @@ struct ft_plan {
   bool no_c_cache = false;  // FT_NO_C_CACHE
   bool relaxed = false;     // FT_RELAXED
   bool fused = true;        // exact factor passes launch in-place items and chunk maps together (not FT_SPLIT_FACTOR)
+  bool run_reuse = false;   // segment passes reuse the column-0 C row along runs (FT_RUN_REUSE)
+  int loss_mode = 0;        // the mode whose CSR the loss and forward passes walk
   std::vector<ft::ModeMeta> meta;
   std::vector<ft::ModeHost> host;
   std::vector<ft::ModeDev> dev;

@@ -323,6 +323,16 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
     H.seg_ptr[i + 1] = (int64_t)H.segs.size();
   }
 
+  // runs of equal column-0 index (mode m + 1) within rows: the segment
+  // passes gather that C row once per run
+  {
+    int64_t runs = 0;
+    const int32_t* c0 = H.idx.data();
+    for (int64_t i = 0; i < I; ++i)
+      for (int64_t p = H.row_ptr[i]; p < H.row_ptr[i + 1]; ++p) runs += (p == H.row_ptr[i] || c0[p] != c0[p - 1]);
+    M.n_runs = runs;
+  }
+
   // share g per fiber when fibers hold 4 elements or more on average: per
   // element, reading g saves about a quarter of the cost of forming it per
   // fiber (measured on MI355X with the Netflix-shaped workload)
@@ -360,6 +370,7 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   inf.fiber_shared = M.use_fiber ? 1 : 0;
   inf.head = P->head;
   inf.chunk = P->chunk;
+  inf.runs = M.n_runs;
   return FT_OK;
 }
 
@@ -490,11 +501,22 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
   P->J = d->J[0];
   P->R = d->R;
   P->nnz = nnz;
-  P->chunk = d->chunk ? d->chunk : 512;
-  P->head = d->head ? d->head : 2 * P->chunk;
+  // Default piece lengths.  Exact passes: a chunk map costs 4 J^2 flops per
+  // element and a fold of maps J^3, while the serial in-place chains run
+  // beside the maps in the same launch, so with J >= 32 longer chunks and
+  // far longer heads pay (measured on MI355X with the Netflix-shaped tensor:
+  // 32.7 ms per iteration with chunk 512 and head 1024, 28.4 with head 16384,
+  // chunk 1024 halving the folds); J = 16 gains less.  Relaxed passes keep
+  // chunk 512 and head 1024: their chunks start from the head's result, so a
+  // long head is serial time, and the chunk length is part of the semantics.
+  const int J0 = d->J[0];
+  const bool rlx = (d->flags & FT_RELAXED) != 0;
+  P->chunk = d->chunk ? d->chunk : (!rlx && J0 >= 32 ? 1024 : 512);
+  P->head = d->head ? d->head : P->chunk * (rlx ? 2 : J0 >= 32 ? 16 : J0 >= 16 ? 8 : 2);
   P->no_c_cache = (d->flags & FT_NO_C_CACHE) != 0;
   P->relaxed = (d->flags & FT_RELAXED) != 0;
   P->fused = !(d->flags & FT_SPLIT_FACTOR);
+  P->run_reuse = (d->flags & FT_RUN_REUSE) && N >= 3;
   P->fanin = std::min(d->fanin ? d->fanin : max_fanin(d->J[0]), max_fanin(d->J[0]));
   try {
     P->meta.resize(N);
@@ -511,6 +533,9 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
       return s;
     }
   }
+  // the loss walks the mode with the fewest runs (longest on average)
+  for (int m = 1; m < N; ++m)
+    if (P->meta[m].n_runs < P->meta[P->loss_mode].n_runs) P->loss_mode = m;
   layout(P);
   P->host_valid = true;
   *out = P;

@@ -39,6 +39,22 @@ __device__ __forceinline__ void load16(const uint16_t* p, float (&o)[8]) {
   }
 }
 
+// a 16-byte slice as loaded, widened to its 4 FP32 or 8 BF16 values
+template <class T>
+__device__ __forceinline__ void widen(const uint4& u, float (&o)[vpl<T>()]) {
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o[c] = __uint_as_float(w[c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      o[2 * c] = __uint_as_float(w[c] << 16);
+      o[2 * c + 1] = __uint_as_float(w[c] & 0xFFFF0000u);
+    }
+  }
+}
+
 // prod over the gathered 16-byte slices (lane q of the element) of its C
 // rows, in table order; zero for an invalid slot.  Invalid slots carry index
 // 0 (a valid row), so the loads need no branch and are all in flight together.
@@ -249,6 +265,262 @@ __global__ __launch_bounds__(256) void k_segsum(const Seg* __restrict__ segs, in
   __syncthreads();
   for (int e = threadIdx.x; e < J * R; e += 256)
     partials[(int64_t)blockIdx.x * J * R + e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+}
+
+// ---------------------------------------------------------------------------
+// Segment passes with the C row of the first index column reused along runs.
+// Within a row of mode m the elements are sorted by the index of mode m + 1
+// (column 0 of idx), so consecutive elements repeat it in runs (at order 3 the
+// fibers of the third mode).  Here the P slots of a wavefront (R/V lanes
+// each) take contiguous pieces of a segment, so that a run stays within a
+// slot, and a slot gathers the column-0 row only where that index changes:
+// per element it gathers the rows of the other columns, per run one more.
+// With u = C(m)[row] * C(m+1)[j] formed once per run,
+//     xhat = u . prod_{k >= 1} C[i_k]                        (per element)
+//     s = sum_x e_x w_x = sum_runs C(m+1)[j] * t_run,  t_run = sum_{x in run} e_x prod_{k >= 1} C[i_k].
+// MODE 0, 1, 2 as in k_segsum; MODE 3: loss (FP64 sum of e^2) and, with out,
+// xhat stored at the element's input position.  The walk, the partials and
+// the fixed summation order are otherwise those of k_segsum: a wavefront
+// takes segments gw, gw + nw, ..., and each trip of U steps loads the indices
+// of the next trip (across segment boundaries) while its gathers are in
+// flight.
+template <int N, int J, int R, int MODE, class T>
+__global__ __launch_bounds__(256) void k_segrun(const Seg* __restrict__ segs, int64_t nseg,
+                                                const int32_t* __restrict__ idx, int64_t nnz,
+                                                const float* __restrict__ val, CPtrs<N, T> cp,
+                                                const T* __restrict__ Cm, const T* __restrict__ Am,
+                                                const float* __restrict__ up, const int32_t* __restrict__ perm,
+                                                float* __restrict__ partials, float* __restrict__ tseg,
+                                                double* __restrict__ dpart, float* __restrict__ out) {
+  static_assert(N >= 3, "run reuse needs a column besides the first");
+  constexpr int V = vpl<T>();
+  constexpr int QL = R / V;               // lanes per element
+  constexpr int P = 64 / QL;              // slots per wavefront
+  constexpr int GJ = (J + P - 1) / P;
+  constexpr int U = N > 4 ? 2 : 4;        // steps per trip
+  constexpr int NL = (U + QL - 1) / QL;   // element loads per lane per trip
+  constexpr int NI = N - 1;
+  constexpr bool LOSS = MODE == 3;
+  constexpr bool PERM = MODE == 2;
+  __shared__ float red[LOSS ? 1 : 4][LOSS ? 1 : J * R];
+  __shared__ double dred[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int slot = lane / QL, q = lane % QL;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  const float* xs = PERM ? up : val;
+  float Gp[LOSS ? 1 : GJ][V];
+#pragma unroll
+  for (int u = 0; u < (LOSS ? 1 : GJ); ++u)
+#pragma unroll
+    for (int c = 0; c < V; ++c) Gp[u][c] = 0.f;
+  double sse = 0.0;
+  // loads of one trip: lane q of a slot loads the slot's elements q, q + QL, ... of the trip
+  struct Ld {
+    int32_t ik[NL][NI];
+    float xv[NL];
+  };
+  auto load_trip = [&](Ld& L, const Seg& X, int k0) {
+    const int Ls = (X.len + P - 1) / P;
+    const int last = max(X.len - 1, 0);
+#pragma unroll
+    for (int h = 0; h < NL; ++h) {
+      const uint32_t o = (uint32_t)min(slot * Ls + k0 + q + QL * h, last);
+#pragma unroll
+      for (int k = 0; k < NI; ++k) L.ik[h][k] = (idx + (int64_t)k * nnz + X.start)[o];
+      L.xv[h] = PERM ? xs[(perm + X.start)[o]] : (xs + X.start)[o];
+    }
+  };
+  auto row_loads = [&](const Seg& X, float (&cr)[V], float (&ar)[LOSS ? 1 : GJ]) {
+    if (MODE != 2) load16(Cm + (int64_t)X.row * R + V * q, cr);
+    if constexpr (!LOSS) {
+#pragma unroll
+      for (int u = 0; u < GJ; ++u) {
+        const int j = slot + P * u;
+        ar[u] = j < J ? to_f(Am[(int64_t)X.row * J + j]) : 0.f;
+      }
+    }
+  };
+  int64_t sg = (int64_t)blockIdx.x * 4 + wave;
+  if (sg < nseg) {
+    const Seg none{0, 0, 0};
+    Seg S = segs[sg];
+    Seg Sq = sg + nw < nseg ? segs[sg + nw] : none;
+    float crow[V], arow[LOSS ? 1 : GJ];
+#pragma unroll
+    for (int c = 0; c < V; ++c) crow[c] = 0.f;
+    row_loads(S, crow, arow);
+    Ld cur;
+    load_trip(cur, S, 0);
+    int Ls = (S.len + P - 1) / P;
+    int b = slot * Ls, e = min(S.len, b + Ls);
+    // run state of this slot: the column-0 index and row of the current run,
+    // u = crow * c1, the run's partial sum t, the segment's sum s
+    int32_t jprev = -1;
+    float c1[V], uu[V], t[V], s[V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) c1[c] = uu[c] = t[c] = s[c] = 0.f;
+    int k0 = 0;
+    for (;;) {
+      int32_t ik[U][NI];
+      float xv[U];
+      bool vl[U], nr[U];
+      static_for<0, U>([&](auto UU) {
+        constexpr int u = decltype(UU)::value;
+        constexpr int h = u / QL;
+        const int src = slot * QL + (u % QL);
+#pragma unroll
+        for (int k = 0; k < NI; ++k) ik[u][k] = QL > 1 ? __shfl(cur.ik[h][k], src) : cur.ik[h][k];
+        xv[u] = QL > 1 ? __shfl(cur.xv[h], src) : cur.xv[h];
+        vl[u] = b + k0 + u < e;
+      });
+      // a step starts a run where its column-0 index differs from the step before
+      nr[0] = vl[0] && ik[0][0] != jprev;
+#pragma unroll
+      for (int u = 1; u < U; ++u) nr[u] = vl[u] && ik[u][0] != ik[u - 1][0];
+      // gathers: the rows of columns 1.. for every step, the column-0 row where a run starts
+      // slices are kept as loaded (four registers, FP32 or BF16) and widened
+      // where used; at order 4 and up the per-element product is formed here
+      constexpr bool PROD = NI > 2;
+      uint4 w2r[U], cnr[U];
+      float w2p[PROD ? U : 1][PROD ? V : 1];
+      const uint32_t qb = (uint32_t)(16 * q);
+      auto slice = [&](int k, int32_t i) {
+        return *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(cp.p[k]) +
+                                               ((uint32_t)i * (uint32_t)(R * sizeof(T)) + qb));
+      };
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        w2r[u] = slice(1, ik[u][1]);
+        if constexpr (PROD) {
+          widen<T>(w2r[u], w2p[u]);
+#pragma unroll
+          for (int k = 2; k < NI; ++k) {
+            float tk[V];
+            widen<T>(slice(k, ik[u][k]), tk);
+#pragma unroll
+            for (int c = 0; c < V; ++c) w2p[u][c] *= tk[c];
+          }
+        }
+        cnr[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (nr[u]) cnr[u] = slice(0, ik[u][0]);
+      }
+      // the next trip's indices (the next segment's first trip at a segment's end)
+      const bool seg_end = k0 + U >= Ls;
+      const Seg& Sn = seg_end ? Sq : S;
+      Ld nxt;
+      load_trip(nxt, Sn, seg_end ? 0 : k0 + U);
+      float crow_n[V], arow_n[LOSS ? 1 : GJ];
+#pragma unroll
+      for (int c = 0; c < V; ++c) crow_n[c] = crow[c];
+#pragma unroll
+      for (int u = 0; u < (LOSS ? 1 : GJ); ++u) arow_n[u] = arow[u];
+      if (seg_end) row_loads(Sq, crow_n, arow_n);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        float w2[V];
+        if constexpr (PROD) {
+#pragma unroll
+          for (int c = 0; c < V; ++c) w2[c] = w2p[u][c];
+        } else {
+          widen<T>(w2r[u], w2);
+        }
+        if (nr[u]) {
+          // close the previous run: s += C(m+1)[j] * t
+          float cn[V];
+          widen<T>(cnr[u], cn);
+#pragma unroll
+          for (int c = 0; c < V; ++c) {
+            s[c] = fmaf(c1[c], t[c], s[c]);
+            t[c] = 0.f;
+            c1[c] = cn[c];
+            uu[c] = crow[c] * c1[c];
+          }
+        }
+        if (vl[u]) jprev = ik[u][0];
+        float d;
+        if constexpr (MODE == 2) {
+          d = vl[u] ? xv[u] : 0.f;
+        } else {
+          float xh = uu[0] * w2[0];
+#pragma unroll
+          for (int c = 1; c < V; ++c) xh = fmaf(uu[c], w2[c], xh);
+          xh = group_sum<QL>(xh);
+          if constexpr (LOSS) {
+            if (vl[u] && q == 0) {
+              const float er = xv[u] - xh;
+              sse += (double)er * (double)er;
+              if (out) out[perm[S.start + (b + k0 + u)]] = xh;
+            }
+            d = 0.f;
+          } else {
+            d = vl[u] ? (MODE == 0 ? xv[u] - xh : xh - xv[u]) : 0.f;
+          }
+        }
+        if constexpr (!LOSS) {
+#pragma unroll
+          for (int c = 0; c < V; ++c) t[c] = fmaf(d, w2[c], t[c]);
+        }
+      }
+      if (seg_end) {
+        if constexpr (!LOSS) {
+#pragma unroll
+          for (int c = 0; c < V; ++c) s[c] = fmaf(c1[c], t[c], s[c]);
+#pragma unroll
+          for (int off = QL; off < 64; off <<= 1)
+#pragma unroll
+            for (int c = 0; c < V; ++c) s[c] += __shfl_xor(s[c], off);
+          if (tseg && slot == 0)
+#pragma unroll
+            for (int c = 0; c < V; ++c) tseg[sg * R + V * q + c] = s[c];
+#pragma unroll
+          for (int u = 0; u < GJ; ++u) {
+            const int j = slot + P * u;
+            if (j < J)
+#pragma unroll
+              for (int c = 0; c < V; ++c) Gp[u][c] = fmaf(arow[u], s[c], Gp[u][c]);
+          }
+        }
+        sg += nw;
+        if (sg >= nseg) break;
+        S = Sq;
+        Sq = sg + nw < nseg ? segs[sg + nw] : none;
+        Ls = (S.len + P - 1) / P;
+        b = slot * Ls;
+        e = min(S.len, b + Ls);
+        jprev = -1;
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          crow[c] = crow_n[c];
+          c1[c] = uu[c] = t[c] = s[c] = 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < (LOSS ? 1 : GJ); ++u) arow[u] = arow_n[u];
+        k0 = 0;
+      } else {
+        k0 += U;
+      }
+      cur = nxt;
+    }
+  }
+  if constexpr (LOSS) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) sse += __shfl_xor(sse, off);
+    if (lane == 0) dred[wave] = sse;
+    __syncthreads();
+    if (threadIdx.x == 0 && dpart) dpart[blockIdx.x] = ((dred[0] + dred[1]) + dred[2]) + dred[3];
+  } else {
+#pragma unroll
+    for (int u = 0; u < GJ; ++u) {
+      const int j = slot + P * u;
+      if (j < J)
+#pragma unroll
+        for (int c = 0; c < V; ++c) red[wave][j * R + V * q + c] = Gp[u][c];
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < J * R; x += 256)
+      partials[(int64_t)blockIdx.x * J * R + x] = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
+  }
 }
 
 // Core gradient without the C cache (the Table 5 comparison; N = 3,
@@ -540,6 +812,24 @@ hipError_t segsum_impl(const ft_plan* P, int m, const ft_params* p, float* parti
   // modes 0 and 1 (the core gradient and the gradient of 1/2 sum e^2) launch
   // the same grid, so their sums run in the same order and one is the exact
   // negation of the other
+  if constexpr (N >= 3) {
+    if (P->run_reuse) {
+      const void* kr = mode == 2 ? (const void*)k_segrun<N, J, R, 2, T> : (const void*)k_segrun<N, J, R, 0, T>;
+      const int nbr = seg_blocks(kr, M.n_segs);
+      *nblocks = nbr;
+      KTimer tm(P, FT_K_SEGSUM, s);
+      if (mode == 0)
+        hipLaunchKernelGGL((k_segrun<N, J, R, 0, T>), dim3(nbr), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz,
+                           D.val, cp, Cm, Am, nullptr, nullptr, partials, tseg, nullptr, nullptr);
+      else if (mode == 1)
+        hipLaunchKernelGGL((k_segrun<N, J, R, 1, T>), dim3(nbr), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz,
+                           D.val, cp, Cm, Am, nullptr, nullptr, partials, tseg, nullptr, nullptr);
+      else
+        hipLaunchKernelGGL((k_segrun<N, J, R, 2, T>), dim3(nbr), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz,
+                           D.val, cp, Cm, Am, up, D.perm, partials, tseg, nullptr, nullptr);
+      return hipGetLastError();
+    }
+  }
   const void* kern = mode == 2 ? (const void*)k_segsum<N, J, R, 2, T> : (const void*)k_segsum<N, J, R, 0, T>;
   const int nb = seg_blocks(kern, M.n_segs);
   *nblocks = nb;
@@ -561,14 +851,27 @@ hipError_t segsum_impl(const ft_plan* P, int m, const ft_params* p, float* parti
 template <int N, int J, int R, class T>
 hipError_t loss_impl(const ft_plan* P, const ft_params* p, double* dpart, double lam_a, double lam_b, double* out4,
                      float* xout, hipStream_t s) {
-  const ModeMeta& M = P->meta[0];
-  const ModeDev& D = P->dev[0];
-  const CPtrs<N, T> cp = others<N, T>(p, 0);
-  const int nb = seg_blocks((const void*)k_loss<N, R, T>, M.n_segs);
-  {
+  // the loss is a sum over all elements: any mode's CSR serves; with run
+  // reuse the plan picks the mode with the longest runs
+  const int lm = P->run_reuse ? P->loss_mode : 0;
+  const ModeMeta& M = P->meta[lm];
+  const ModeDev& D = P->dev[lm];
+  const CPtrs<N, T> cp = others<N, T>(p, lm);
+  int nb = 0;
+  if constexpr (N >= 3) {
+    if (P->run_reuse) {
+      nb = seg_blocks((const void*)k_segrun<N, J, R, 3, T>, M.n_segs);
+      KTimer tm(P, FT_K_LOSS, s);
+      hipLaunchKernelGGL((k_segrun<N, J, R, 3, T>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz,
+                         D.val, cp, Store<T>::C(p, lm), nullptr, nullptr, D.perm, nullptr, nullptr,
+                         out4 ? dpart : nullptr, xout);
+    }
+  }
+  if (nb == 0) {
+    nb = seg_blocks((const void*)k_loss<N, R, T>, M.n_segs);
     KTimer tm(P, FT_K_LOSS, s);
     hipLaunchKernelGGL((k_loss<N, R, T>), dim3(nb), dim3(256), 0, s, D.segs, M.n_segs, D.idx, P->nnz, D.val, cp,
-                       Store<T>::C(p, 0), out4 ? dpart : nullptr, D.perm, xout);
+                       Store<T>::C(p, lm), out4 ? dpart : nullptr, D.perm, xout);
   }
   if (!out4) return hipGetLastError();
   // the regularisers of Eq. (6) are taken on the FP32 masters

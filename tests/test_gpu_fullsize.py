@@ -29,8 +29,10 @@ def netflix():
     return w, c, v, A, B, plan, prm
 
 
-def _sample_rows(counts, chunk=512, head=1024):
-    """The longest rows and rows near the piece boundaries of the default plan (head, then chunks)."""
+def _sample_rows(counts, plan):
+    """The longest rows and rows near the piece boundaries of the plan (head, then chunks)."""
+    info = plan.mode_info(0)
+    head, chunk = info["head"], info["chunk"]
     order = np.argsort(-counts, kind="stable")
     picks = [order[0], order[min(5, len(order) - 1)]]
     for target in (head + chunk * 3 + 7, head + 1, head, head // 2, chunk + 1, 3):
@@ -63,7 +65,7 @@ def test_factor_passes_sampled_rows(netflix):
         ft.factor_pass(plan, prm, m, w.lr, w.lam)
         torch.cuda.synchronize()
         counts = np.bincount(c[m], minlength=w.dims[m])
-        rows = _sample_rows(counts)
+        rows = _sample_rows(counts, plan)
         sel = np.isin(c[m], rows)
         print(f"[fullsize] mode {m}: rows {rows.tolist()} lengths {counts[rows].tolist()}", flush=True)
         orc = oracle.Model(w.dims, w.J, R, np.ascontiguousarray(c[:, sel]), v[sel].astype(np.float64), A_now, B_now)
@@ -95,11 +97,12 @@ def test_relaxed_factor_passes_sampled_rows(netflix):
         ft.factor_pass(plan, prm, m, w.lr, w.lam)
         torch.cuda.synchronize()
         counts = np.bincount(c[m], minlength=w.dims[m])
-        rows = _sample_rows(counts)
+        rows = _sample_rows(counts, plan)
         sel = np.isin(c[m], rows)
         print(f"[fullsize relaxed] mode {m}: rows {rows.tolist()} lengths {counts[rows].tolist()}", flush=True)
         orc = oracle.Model(w.dims, w.J, R, np.ascontiguousarray(c[:, sel]), v[sel].astype(np.float64), A_now, B_now)
-        orc.factor_pass_relaxed(m, w.lr, w.lam, 1024, 512)
+        info = plan.mode_info(m)
+        orc.factor_pass_relaxed(m, w.lr, w.lam, info["head"], info["chunk"])
         got = to_np(prm.A[m])[rows]
         want = orc.A[m][rows]
         before = A_now[m][rows]

@@ -21,7 +21,7 @@ CASES = [
     ("zipf3_j16_smallchunk", [3000, 400, 60], 60_000, 1.1, 16, 16, {"chunk": 16, "fanin": 4}),
     ("zipf3_j32", [1500, 200, 40], 60_000, 1.1, 32, 32, {"chunk": 32, "fanin": 8}),
     ("zipf4_j8", [400, 300, 200, 50], 80_000, 1.1, 8, 8, {"chunk": 24, "fanin": 3}),
-    ("zipf4_j32", [500, 300, 100, 40], 40_000, 1.1, 32, 32, {}),
+    ("zipf4_j32", [500, 300, 100, 40], 40_000, 1.1, 32, 32, {"chunk": 64, "head": 256}),
     ("zipf8_j8r16", [30, 25, 20, 20, 15, 15, 10, 10], 40_000, 1.05, 8, 16, {"chunk": 40}),
 ]
 IDS = [c[0] for c in CASES]

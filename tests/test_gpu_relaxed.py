@@ -26,9 +26,9 @@ CASES = [
 LR, LAM = 1e-3, 1e-2
 
 
-def _heads(kw):
-    chunk = kw.get("chunk", 512)
-    return kw.get("head", 2 * chunk), chunk
+def _heads(plan):
+    info = plan.mode_info(0)
+    return info["head"], info["chunk"]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
@@ -42,7 +42,7 @@ def test_relaxed_factor_passes(case):
     plan, prm = gpu_setup(dims, J, R, c, v, A, B, storage=storage, relaxed=True, **kw)
     assert sum(plan.mode_info(m)["heavy_rows"] for m in range(N)) > 0
     orc = oracle_model(dims, J, R, c, v, A, B)
-    head, chunk = _heads(kw)
+    head, chunk = _heads(plan)
     if name.endswith("guard"):
         # the longest mode-0 row: lr sum ||g||^2 over its chunked elements is above 1
         w = np.prod([orc.C[n][c[n]] for n in range(1, N)], axis=0)

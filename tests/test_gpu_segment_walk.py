@@ -174,3 +174,32 @@ def _core_pass(walk_case, storage):
             dj = np.linalg.norm(want[j] - B0[j])
             err = np.linalg.norm(got[j] - want[j])
             assert err <= 1e-3 * dj + 1e-6 * np.linalg.norm(want[j]), (name, storage, m, j, err, dj)
+
+
+def test_run_reuse_matches_per_element_gathers(walk_case):
+    """With FT_RUN_REUSE the segment passes gather the C row of mode m + 1 once per run of elements sharing
+    it; the default walk gathers it for every element.  Both compute the same sums in a different order:
+    loss, forward, gradient and core gradient agree to FP32 rounding, so the oracle checks of the default
+    walk above carry over."""
+    import paper_2210_06014_amd as ft
+
+    name, dims, J, R, c, v, A, B, exact16, plan, orc, ref = walk_case
+    reuse = ft.Plan(dims, J, R, c, v, with_perm=True, run_reuse=True)
+    for m in range(len(dims)):
+        assert reuse.mode_info(m)["runs"] < reuse.nnz
+    for storage in _storages(exact16):
+        got, base = {}, {}
+        for tag, pl in (("reuse", reuse), ("plain", plan)):
+            prm = _params((name, dims, J, R, c, v, A, B, exact16, pl, orc, ref), storage)
+            out = {"loss": to_np(ft.loss(pl, prm)), "fwd": to_np(ft.forward(pl, prm))}
+            gA, gB = ft.grad(pl, prm)
+            for n in range(len(dims)):
+                out[f"gA{n}"], out[f"gB{n}"] = to_np(gA[n]), to_np(gB[n])
+                out[f"G{n}"] = to_np(ft.core_grad(pl, prm, n))
+            (got if tag == "reuse" else base).update(out)
+        np.testing.assert_allclose(got["loss"][:2], base["loss"][:2], rtol=1e-6)
+        assert np.all(np.abs(got["fwd"] - base["fwd"]) <= 1e-6 * ref["scale"] + 1e-30), (name, storage)
+        for n in range(len(dims)):
+            for k in (f"gA{n}", f"gB{n}", f"G{n}"):
+                d = np.linalg.norm(got[k] - base[k])
+                assert d <= 1e-5 * np.linalg.norm(base[k]), (name, storage, k, d)

@@ -32,6 +32,27 @@ def _plan(dims, J, R, coords, vals, **kw):
     return ft.Plan(dims, J, R, coords, vals, keep_host=True, upload=False, **kw)
 
 
+@pytest.mark.parametrize("order", [3, 4, 8])
+def test_run_counts(order):
+    """The segment passes gather the C row of mode m + 1 once per run of a row's elements sharing that index;
+    the plan's run count per mode is the number of (row, index of mode m + 1) changes along its sorted CSR,
+    which for order 3 is the number of fibers of mode m + 2 (the elements with both fixed)."""
+    dims = [40, 30, 20, 9, 8, 7, 6, 5][:order]
+    c, _ = synth.coords(dims, 5000, 1.1, seed=9)
+    v = synth.values(5000, "int1to5", seed=9)
+    plan = _plan(dims, 8, 8 if order < 8 else 16, c, v)
+    for m in range(order):
+        row_ptr, idx, _, _ = plan.host_csr(m)
+        rows = np.repeat(np.arange(dims[m]), np.diff(row_ptr))
+        new = np.ones(c.shape[1], dtype=bool)
+        new[1:] = (rows[1:] != rows[:-1]) | (idx[0][1:] != idx[0][:-1])
+        assert plan.mode_info(m)["runs"] == int(new.sum()), m
+        if order == 3:
+            other = (m + 2) % 3
+            pairs = {(int(a), int(b)) for a, b in zip(c[m], c[(m + 1) % 3])}
+            assert len(pairs) == plan.mode_info(other)["fibers"] == int(new.sum())
+
+
 @pytest.mark.parametrize("order", [3, 4])
 def test_csr_order_and_permutation(order):
     dims = [37, 23, 11, 7][:order]
