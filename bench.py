@@ -119,8 +119,7 @@ def cpu_baseline(w, c, v, A, B, sample):
     }
 
 
-COUNTER_FILES = {("netflix", "f32"): "profiles/netflix_j16_fp32_hbm_counters.md",
-                 ("netflix32", "f32"): "profiles/netflix32_fp32_hbm_counters.md",
+COUNTER_FILES = {("netflix32", "f32"): "profiles/netflix32_fp32_hbm_counters.md",
                  ("netflix32", "bf16"): "profiles/netflix32_bf16_hbm_counters.md"}
 KERNEL_SOURCES = ["ft_device.h", "ft_refresh.hip", "ft_factor.hip", "ft_segment.hip"]
 
@@ -302,9 +301,15 @@ def rooflines(w, nnz, c, plan, prof, steps, storage, head, relaxed, counters_ok)
                           "executed_frac": ex / PEAK_FP32_TFLOPS})
             return r
         ach = byts / t_s / 1e9
-        return {"kernel": k, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "algorithmic_per_launch": byts / launches,
-                "avg_launch_us": kernels[k]["avg_launch_us"]}
+        r = {"kernel": k, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+             "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "algorithmic_per_launch": byts / launches,
+             "avg_launch_us": kernels[k]["avg_launch_us"]}
+        if k in ("segsum", "loss"):
+            # the bytes against HBM are the stream; the gathered C rows come through the caches, and
+            # the CU's vector-memory data path is what saturates (rocprofv3 TD/TA busy counters)
+            r["limiter"] = ("vector-memory data path of the CUs (TD 93-96 % busy, TA 85-91 %), "
+                            "profiles/netflix32_fp32_segment_pass_limiter.md")
+        return r
 
     dom = gather = None
     if kernels:
@@ -388,7 +393,8 @@ def main():
                     help="one workload and storage (default: the metric run, netflix32 FP32 and BF16 legs)")
     ap.add_argument("--nnz", type=int, default=None, help="override the element count (smaller test runs)")
     ap.add_argument("--cpu-sample", type=int, default=None,
-                    help="elements of the oracle's CPU sample (default: 4M at J = R = 16, scaled by (16/J)^2)")
+                    help="elements of the oracle's CPU sample (default: 12M at J = R = 16, scaled by (16/J)^2: "
+                    "about 15 s of oracle time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-planted", action="store_true", help="metric run without the matched-RMSE curves")
     ap.add_argument("--planted-iters", type=int, default=20)
@@ -478,7 +484,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        sample = args.cpu_sample or int(4_000_000 * (16 / max(J, 16)) ** 2)
+        sample = args.cpu_sample or int(12_000_000 * (16 / max(J, 16)) ** 2)
         s = min(sample, nnz)
         log(f"CPU baseline: oracle on {s} elements")
         cpu = cpu_baseline(w, c, v, A, B, s)
