@@ -38,7 +38,7 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic(w, nnz, row_counts, head, fibers, relaxed=False, sp=4):
+def algorithmic(w, nnz, row_counts, heads, fibers, relaxed=False, sp=4):
     """Per-epoch algorithmic flops and bytes per kernel family (formulas in the design notes).
 
     fibers[m] is the number of mode-m fibers when g = B(m) w is shared per fiber
@@ -60,6 +60,7 @@ def algorithmic(w, nnz, row_counts, head, fibers, relaxed=False, sp=4):
     a_read = [d * J * sp for d in w.dims]
     for m in range(N):
         L = row_counts[m]
+        head = heads[m]
         heavy = L > head
         comp = float(np.sum(np.where(heavy, L - head, 0)))
         app = float(nnz - comp)
@@ -270,7 +271,7 @@ def time_passes(ft, plan, prm, w, steps):
             "note": "wall time of factor_epoch and core_epoch calls, timed apart after the measured steps"}
 
 
-def rooflines(w, nnz, c, plan, prof, steps, storage, head, relaxed, counters_ok):
+def rooflines(w, nnz, c, plan, prof, steps, storage, relaxed, counters_ok):
     """Per-kernel rates, the roofline object of the dominant kernel and that of the core gather pass."""
     import numpy as np
 
@@ -278,7 +279,8 @@ def rooflines(w, nnz, c, plan, prof, steps, storage, head, relaxed, counters_ok)
     counts = [np.bincount(c[m], minlength=w.dims[m]) for m in range(N)]
     infos = [plan.mode_info(m) for m in range(N)]
     fibers = [info["fibers"] if info["fiber_shared"] else None for info in infos]
-    alg = algorithmic(w, nnz, counts, head, fibers, relaxed, sp=2 if storage == "bf16" else 4)
+    heads = [info["head"] for info in infos]
+    alg = algorithmic(w, nnz, counts, heads, fibers, relaxed, sp=2 if storage == "bf16" else 4)
     kernels = {}
     for k, (ms, n) in prof.items():
         if n:
@@ -330,17 +332,17 @@ def leg(ft, w, c, plan, A, B, storage, args, nnz, relaxed=False):
     ft.refresh(plan, prm)
     ms, prof, rmse0, rmse = time_steps(ft, plan, prm, w, args.steps, args.warmup, not args.no_profile)
     log(f"{w.name} {storage}: {ms:.3f} ms/step, RMSE {rmse0:.7f} -> {rmse:.7f}")
-    head = plan.mode_info(0)["head"]
     counters_ok = (args.nnz is None and not args.chunk and not args.head and not args.no_fiber_share
                    and not args.no_c_cache and not relaxed and not args.split_factor and not args.run_reuse)
-    kernels, dom, gather, infos, fibers = rooflines(w, nnz, c, plan, prof, args.steps, storage, head, relaxed,
+    kernels, dom, gather, infos, fibers = rooflines(w, nnz, c, plan, prof, args.steps, storage, relaxed,
                                                     counters_ok)
     passes = time_passes(ft, plan, prm, w, args.steps)
     N = len(w.dims)
     return {"storage": storage, "value": 2 * N * nnz / (ms / 1e3), "ms_per_step": ms, "rmse_start": rmse0,
             "rmse_end": rmse, "roofline": dom, "roofline_gather": gather, "passes": passes, "kernels": kernels,
             "fiber_shared_modes": [m for m in range(N) if fibers[m] is not None],
-            "fibers_per_mode": [info["fibers"] for info in infos]}
+            "fibers_per_mode": [info["fibers"] for info in infos],
+            "heads_per_mode": [info["head"] for info in infos], "chunk": infos[0]["chunk"]}
 
 
 def describe(w, nnz):
@@ -513,6 +515,8 @@ def main():
                               if args.relaxed else "exact serial SGD per row"),
             "fiber_shared_modes": main_leg["fiber_shared_modes"],
             "fibers_per_mode": main_leg["fibers_per_mode"],
+            "heads_per_mode": main_leg["heads_per_mode"],
+            "chunk": main_leg["chunk"],
             "rmse_start": main_leg["rmse_start"],
             "rmse_end": main_leg["rmse_end"],
         },

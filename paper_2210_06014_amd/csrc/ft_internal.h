@@ -142,6 +142,7 @@ struct ModeMeta {
   int64_t n_relax = 0;         // FT_RELAXED level-2 items (heavy rows)
   int64_t n_fibers = 0;
   int64_t n_runs = 0;  // runs of equal column-0 index within rows
+  int64_t head = 0;    // elements of a long row updated in place before its chunk maps
   bool use_fiber = false;
   ft_mode_info info{};
 };
@@ -157,7 +158,8 @@ struct ft_plan {
   ft_desc desc{};
   int N = 0, J = 0, R = 0;
   int64_t nnz = 0;
-  int chunk = 512, head = 1024, fanin = 16;
+  int chunk = 512, head = 1024, fanin = 16;  // head 0: chosen per mode (ModeMeta::head), at most head_cap
+  int64_t head_cap = 0;
   bool no_c_cache = false;  // FT_NO_C_CACHE
   bool relaxed = false;     // FT_RELAXED
   bool fused = true;        // exact factor passes launch in-place items and chunk maps together (not FT_SPLIT_FACTOR)

@@ -4,6 +4,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <thread>
 
@@ -175,8 +176,33 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   // the core, loss and gradient passes keep the sorted arrays, whose
   // neighbouring elements share the next mode's index (cache locality of the
   // gathers).
-  if (P->relaxed && P->head > 0) {
-    const int64_t hl0 = P->head;
+  // head length of this mode: the plan's, or (exact plans by default) the
+  // largest chunk * 2^k, from two chunks up to the plan's cap, that is not
+  // above L_q, the row length reached by the longest rows holding a quarter
+  // of the mode's elements.  Those rows then still split into chunk maps,
+  // which run beside their heads; a head as long as such a row would leave
+  // it one slow serial chain (rows of 10000 elements at order 4: 36 ms per
+  // iteration with head 8192, 52 ms with 16384).  Zipf rows give L_q far
+  // above the cap.
+  M.head = P->head;
+  if (M.head == 0) {
+    std::vector<int64_t> lens;
+    lens.reserve((size_t)I);
+    for (int64_t i = 0; i < I; ++i)
+      if (H.row_ptr[i + 1] > H.row_ptr[i]) lens.push_back(H.row_ptr[i + 1] - H.row_ptr[i]);
+    std::sort(lens.begin(), lens.end(), std::greater<int64_t>());
+    int64_t acc = 0, lq = 0;
+    for (int64_t L : lens) {
+      acc += L;
+      lq = L;
+      if (4 * acc >= nnz) break;
+    }
+    int64_t h = 2 * P->chunk;
+    while (2 * h <= lq && 2 * h <= P->head_cap) h *= 2;
+    M.head = h;
+  }
+  if (P->relaxed && M.head > 0) {
+    const int64_t hl0 = M.head;
     int64_t maxL = 0;
     for (int64_t i = 0; i < I; ++i) maxL = std::max(maxL, H.row_ptr[i + 1] - H.row_ptr[i]);
     if (maxL > hl0) {
@@ -213,7 +239,7 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   // factor work lists: a row of at most `head` elements is one serial item;
   // a longer row is a head item (its first `head` elements, updated in
   // place) followed by chunk items whose maps the combine applies in order
-  const int64_t chunk = P->chunk, hl = P->head;
+  const int64_t chunk = P->chunk, hl = M.head;
   std::vector<FItem> light, head;
   int64_t n_heavy = 0, n_maps = 0, max_row = 0, nonempty = 0;
   std::vector<int64_t> heavy_rows, heavy_base, heavy_nmaps;
@@ -368,7 +394,7 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   inf.combine_levels = (int32_t)H.levels.size();
   inf.fibers = M.n_fibers;
   inf.fiber_shared = M.use_fiber ? 1 : 0;
-  inf.head = P->head;
+  inf.head = (int32_t)M.head;
   inf.chunk = P->chunk;
   inf.runs = M.n_runs;
   return FT_OK;
@@ -506,13 +532,20 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
   // beside the maps in the same launch, so with J >= 32 longer chunks and
   // far longer heads pay (measured on MI355X with the Netflix-shaped tensor:
   // 32.7 ms per iteration with chunk 512 and head 1024, 28.4 with head 16384,
-  // chunk 1024 halving the folds); J = 16 gains less.  Relaxed passes keep
-  // chunk 512 and head 1024: their chunks start from the head's result, so a
-  // long head is serial time, and the chunk length is part of the semantics.
+  // chunk 1024 halving the folds); J = 16 gains less.  Only at orders 3 and 4:
+  // above them a chain step waits on its gathers (the in-place code keeps one
+  // batch of them in flight), and long heads turn rows of similar length into
+  // slow serial chains (order 6, 10000 rows of 10000 elements per mode:
+  // 138 ms with head 16384, 94 ms with 2048).  Relaxed passes keep chunk 512
+  // and head 1024: their chunks start from the head's result, so a long head
+  // is serial time, and the chunk length is part of the semantics.
   const int J0 = d->J[0];
   const bool rlx = (d->flags & FT_RELAXED) != 0;
+  const int long_heads = rlx ? 2 : J0 >= 32 ? (N > 4 ? 4 : 16) : J0 >= 16 ? (N > 4 ? 2 : 8) : 2;
   P->chunk = d->chunk ? d->chunk : (!rlx && J0 >= 32 ? 1024 : 512);
-  P->head = d->head ? d->head : P->chunk * (rlx ? 2 : J0 >= 32 ? 16 : J0 >= 16 ? 8 : 2);
+  // an explicit head, the relaxed default, or 0: each mode picks its own up to head_cap
+  P->head = d->head ? d->head : rlx ? 2 * P->chunk : 0;
+  P->head_cap = (int64_t)P->chunk * long_heads;
   P->no_c_cache = (d->flags & FT_NO_C_CACHE) != 0;
   P->relaxed = (d->flags & FT_RELAXED) != 0;
   P->fused = !(d->flags & FT_SPLIT_FACTOR);

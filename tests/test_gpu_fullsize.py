@@ -29,9 +29,9 @@ def netflix():
     return w, c, v, A, B, plan, prm
 
 
-def _sample_rows(counts, plan):
-    """The longest rows and rows near the piece boundaries of the plan (head, then chunks)."""
-    info = plan.mode_info(0)
+def _sample_rows(counts, plan, m):
+    """The longest rows and rows near the piece boundaries of mode m's plan (head, then chunks)."""
+    info = plan.mode_info(m)
     head, chunk = info["head"], info["chunk"]
     order = np.argsort(-counts, kind="stable")
     picks = [order[0], order[min(5, len(order) - 1)]]
@@ -65,7 +65,7 @@ def test_factor_passes_sampled_rows(netflix):
         ft.factor_pass(plan, prm, m, w.lr, w.lam)
         torch.cuda.synchronize()
         counts = np.bincount(c[m], minlength=w.dims[m])
-        rows = _sample_rows(counts, plan)
+        rows = _sample_rows(counts, plan, m)
         sel = np.isin(c[m], rows)
         print(f"[fullsize] mode {m}: rows {rows.tolist()} lengths {counts[rows].tolist()}", flush=True)
         orc = oracle.Model(w.dims, w.J, R, np.ascontiguousarray(c[:, sel]), v[sel].astype(np.float64), A_now, B_now)
@@ -97,7 +97,7 @@ def test_relaxed_factor_passes_sampled_rows(netflix):
         ft.factor_pass(plan, prm, m, w.lr, w.lam)
         torch.cuda.synchronize()
         counts = np.bincount(c[m], minlength=w.dims[m])
-        rows = _sample_rows(counts, plan)
+        rows = _sample_rows(counts, plan, m)
         sel = np.isin(c[m], rows)
         print(f"[fullsize relaxed] mode {m}: rows {rows.tolist()} lengths {counts[rows].tolist()}", flush=True)
         orc = oracle.Model(w.dims, w.J, R, np.ascontiguousarray(c[:, sel]), v[sel].astype(np.float64), A_now, B_now)

@@ -16,9 +16,9 @@ from tests.gpu_common import bf16_scale, delta_ok, to_np
 pytestmark = pytest.mark.gpu
 
 
-def _sample_rows(counts, plan, max_len=None):
-    """The longest rows and rows near the piece boundaries of the plan (head, then chunks)."""
-    info = plan.mode_info(0)
+def _sample_rows(counts, plan, m, max_len=None):
+    """The longest rows and rows near the piece boundaries of mode m's plan (head, then chunks)."""
+    info = plan.mode_info(m)
     head, chunk = info["head"], info["chunk"]
     order = np.argsort(-counts, kind="stable")
     if max_len is not None:
@@ -41,7 +41,7 @@ def _factor_sampled(w, c, v, plan, prm, tol):
         ft.factor_pass(plan, prm, m, w.lr, w.lam)
         torch.cuda.synchronize()
         counts = np.bincount(c[m], minlength=w.dims[m])
-        rows = _sample_rows(counts, plan)
+        rows = _sample_rows(counts, plan, m)
         sel = np.isin(c[m], rows)
         print(f"[fullsize {w.name}] mode {m}: lengths {counts[rows].tolist()}", flush=True)
         orc = oracle.Model(w.dims, w.J, w.R, np.ascontiguousarray(c[:, sel]), v[sel].astype(np.float64), A_now, B_now)
@@ -98,7 +98,7 @@ def test_order4_autograd_fullsize():
     # gradient rows: dA(n)[i] = sum_{x in row i} -(x - xhat_x) g(n)_x
     for n in range(N):
         counts = np.bincount(c[n], minlength=w.dims[n])
-        rows = _sample_rows(counts, plan, max_len=100_000)
+        rows = _sample_rows(counts, plan, n, max_len=100_000)
         sel = np.isin(c[n], rows)
         print(f"[fullsize order4] mode {n}: gradient rows with lengths {counts[rows].tolist()}", flush=True)
         sub = oracle.Model(w.dims, w.J, w.R, np.ascontiguousarray(c[:, sel]), v[sel].astype(np.float64), A64, B64)

@@ -245,3 +245,39 @@ def test_refuses_dims_beyond_32bit_gather_offsets():
         assert e.value.status == 2
     ok = _plan([lim - 1, 5, 5], R, R, c, v)
     assert ok.mode_info(0)["rows"] == lim - 1
+
+
+def test_default_head_per_mode():
+    """Exact plans pick each mode's head: the largest chunk * 2^k from two chunks up to the cap (16 chunks of
+    1024 at J = 32 and order 3) not above the row length reached by the longest rows holding a quarter of
+    the mode's elements; an explicit head and relaxed plans (two chunks) are kept as given."""
+    dims, J, R = [40, 50, 2], 32, 32
+    c = np.stack(np.meshgrid(np.arange(40), np.arange(50), np.arange(2), indexing="ij")).reshape(3, -1)
+    c = np.repeat(c, 1, axis=1).astype(np.int32)
+    # every cell once: rows of 100 (mode 0), 80 (mode 1) and 2000 elements (mode 2)
+    v = np.ones(c.shape[1], dtype=np.float32)
+
+    def q25(m):
+        L = np.sort(np.bincount(c[m], minlength=dims[m]))[::-1]
+        cs = np.cumsum(L)
+        return int(L[np.searchsorted(cs, cs[-1] / 4)])
+
+    def rule(lq, chunk, cap):
+        h = 2 * chunk
+        while 2 * h <= lq and 2 * h <= cap:
+            h *= 2
+        return h
+
+    for chunk in (16, 64):
+        plan = _plan(dims, J, R, c, v, chunk=chunk)
+        for m in range(3):
+            info = plan.mode_info(m)
+            assert info["chunk"] == chunk
+            assert info["head"] == rule(q25(m), chunk, 16 * chunk), (chunk, m, info["head"], q25(m))
+    assert [_plan(dims, J, R, c, v, chunk=16, head=48).mode_info(m)["head"] for m in range(3)] == [48] * 3
+    assert [_plan(dims, J, R, c, v, chunk=16, relaxed=True).mode_info(m)["head"] for m in range(3)] == [32] * 3
+    # a Zipf mode whose long rows hold most elements takes the cap
+    cz, _ = synth.coords([4000, 30, 20], 60000, 1.3, seed=3)
+    vz = synth.values(60000, "int1to5", seed=3)
+    pz = _plan([4000, 30, 20], J, R, cz, vz, chunk=16)
+    assert pz.mode_info(2)["head"] == 16 * 16
