@@ -105,11 +105,13 @@ typedef struct {
   int32_t head;                 /* rows of at most this many elements are updated as one serial chain; a
                                    longer row has its first `head` elements updated in place and the rest
                                    cut into chunks.  0: with FT_RELAXED, 2 chunks; otherwise each mode
-                                   takes the largest chunk * 2^k, from 2 chunks up to a cap, not above
-                                   the row length reached by the longest rows holding a quarter of its
-                                   elements; the cap is 16 chunks for J >= 32 (4 above order 4), 8 for
-                                   J = 16 (2 above order 4), 2 otherwise.  ft_plan_mode_info reports
-                                   the value each mode uses */
+                                   takes the longest of 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32 chunks,
+                                   up to a cap (32 chunks for J >= 32, 24 for J = 16, 2 otherwise), that
+                                   is not above the row length reached by the longest rows holding a
+                                   quarter of its elements and whose serial chain a cost model of the
+                                   launch (from the row lengths and whether g is shared per fiber)
+                                   expects to end within the launch.  ft_plan_mode_info reports the
+                                   value each mode uses */
   int32_t fanin;                /* chunk maps folded per combine step (0 or above the maximum: 16 for
                                    J <= 16, 8 above); a row with at most fanin maps has them applied in
                                    sequence to its head's result */

@@ -86,6 +86,14 @@ static void radix_by_column(const int32_t* key, int64_t dim, std::vector<uint32_
   }
 }
 
+// share g per fiber when fibers hold 4 elements or more on average: per
+// element, reading g saves about a quarter of the cost of forming it per
+// fiber (measured on MI355X with the Netflix-shaped workload)
+static bool fiber_share(uint32_t flags, int64_t n_fibers, int64_t nnz) {
+  return !(flags & (FT_NO_FIBER_SHARE | FT_NO_C_CACHE)) && n_fibers > 0 && n_fibers * 4 <= nnz &&
+         n_fibers <= 0x7FFFFFFF;
+}
+
 static void pad4(std::vector<FItem>& v, int32_t kind) {
   while (v.size() % 4) v.push_back(FItem{0, 0, 0, 0, kind});
 }
@@ -177,13 +185,25 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
   // neighbouring elements share the next mode's index (cache locality of the
   // gathers).
   // head length of this mode: the plan's, or (exact plans by default) the
-  // largest chunk * 2^k, from two chunks up to the plan's cap, that is not
-  // above L_q, the row length reached by the longest rows holding a quarter
-  // of the mode's elements.  Those rows then still split into chunk maps,
-  // which run beside their heads; a head as long as such a row would leave
-  // it one slow serial chain (rows of 10000 elements at order 4: 36 ms per
-  // iteration with head 8192, 52 ms with 16384).  Zipf rows give L_q far
-  // above the cap.
+  // longest of 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32 chunks, up to the
+  // plan's cap, that passes two tests.
+  //  * Not above L_q, the row length reached by the longest rows holding a
+  //    quarter of the mode's elements.  Those rows then still split into
+  //    chunk maps, which run beside their heads; a head as long as such a row
+  //    would leave it one slow serial chain (rows of 10000 elements at order
+  //    4: 36 ms per iteration with head 8192, 52 ms with 16384).  Zipf rows
+  //    give L_q far above the cap.
+  //  * The serial chain of a head must not outlast the rest of the launch.
+  //    With S(h) elements on in-place chains and M(h) in chunk maps, the
+  //    launch costs about t_m (r_s S + M) and a head of h elements a h, so
+  //    the test is r_a h <= 0.8 (r_s S + M), r_a = a / t_m and r_s = t_s /
+  //    t_m.  A chain step forms g (J R FMAs on 16 lanes) unless the mode
+  //    shares g per fiber; a map step adds the J x J update.  Fitted to
+  //    MI355X launch times of the Netflix-shaped tensors and the 1000^3
+  //    density tensors: r_a = 2358 (J = 32), 3100 (J = 16) with g formed per
+  //    step, 1200 and 2000 with g read; r_s = 0.5 and 0.2 / 0.3.  This is
+  //    what shortens the heads of tensors with few long rows (1000 rows of
+  //    20000 elements: 5120 instead of 16384, 2.2 instead of 4.8 ms per pass).
   M.head = P->head;
   if (M.head == 0) {
     std::vector<int64_t> lens;
@@ -197,8 +217,24 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
       lq = L;
       if (4 * acc >= nnz) break;
     }
+    const bool shares_g = fiber_share(P->desc.flags, M.n_fibers, nnz);
+    const double ra = P->J >= 32 ? (shares_g ? 1200.0 : 2358.0) : (shares_g ? 2000.0 : 3100.0);
+    const double rs = shares_g ? (P->J >= 32 ? 0.2 : 0.3) : 0.5;
+    const int64_t maxL = lens.empty() ? 0 : lens[0];
+    static const int kChunks[] = {2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32};
     int64_t h = 2 * P->chunk;
-    while (2 * h <= lq && 2 * h <= P->head_cap) h *= 2;
+    for (int k : kChunks) {
+      const int64_t c = (int64_t)k * P->chunk;
+      if (k == 2) continue;
+      if (c > P->head_cap || c > lq) break;
+      double S = 0.0, Mm = 0.0;
+      for (int64_t L : lens) {
+        S += (double)std::min(L, c);
+        Mm += (double)std::max<int64_t>(L - c, 0);
+      }
+      if (ra * (double)std::min(c, maxL) > 0.8 * (rs * S + Mm)) break;
+      h = c;
+    }
     M.head = h;
   }
   if (P->relaxed && M.head > 0) {
@@ -359,11 +395,7 @@ static ft_status build_mode(ft_plan* P, int m, const int32_t* coords, const floa
     M.n_runs = runs;
   }
 
-  // share g per fiber when fibers hold 4 elements or more on average: per
-  // element, reading g saves about a quarter of the cost of forming it per
-  // fiber (measured on MI355X with the Netflix-shaped workload)
-  M.use_fiber = !(P->desc.flags & (FT_NO_FIBER_SHARE | FT_NO_C_CACHE)) && M.n_fibers > 0 && M.n_fibers * 4 <= nnz &&
-                M.n_fibers <= 0x7FFFFFFF;
+  M.use_fiber = fiber_share(P->desc.flags, M.n_fibers, nnz);
   if (!M.use_fiber) {
     H.fid.clear();
     H.fid.shrink_to_fit();
@@ -531,17 +563,16 @@ extern "C" ft_status ft_plan_create(ft_plan** out, const ft_desc* d, const int32
   // element and a fold of maps J^3, while the serial in-place chains run
   // beside the maps in the same launch, so with J >= 32 longer chunks and
   // far longer heads pay (measured on MI355X with the Netflix-shaped tensor:
-  // 32.7 ms per iteration with chunk 512 and head 1024, 28.4 with head 16384,
-  // chunk 1024 halving the folds); J = 16 gains less.  Only at orders 3 and 4:
-  // above them a chain step waits on its gathers (the in-place code keeps one
-  // batch of them in flight), and long heads turn rows of similar length into
-  // slow serial chains (order 6, 10000 rows of 10000 elements per mode:
-  // 138 ms with head 16384, 94 ms with 2048).  Relaxed passes keep chunk 512
-  // and head 1024: their chunks start from the head's result, so a long head
-  // is serial time, and the chunk length is part of the semantics.
+  // 32.7 ms per iteration with chunk 512 and head 1024, 26.7 with chunk 1024
+  // and head 24576); J = 16 gains less (11.4 ms with head 4096, 11.0 with
+  // 12288).  Each mode picks its head up to the cap (32 chunks at J >= 32,
+  // 24 at J = 16, 2 below) from its row lengths, as build_mode describes.
+  // Relaxed passes keep chunk 512 and head 1024: their chunks start from the
+  // head's result, so a long head is serial time, and the chunk length is
+  // part of the semantics.
   const int J0 = d->J[0];
   const bool rlx = (d->flags & FT_RELAXED) != 0;
-  const int long_heads = rlx ? 2 : J0 >= 32 ? (N > 4 ? 4 : 16) : J0 >= 16 ? (N > 4 ? 2 : 8) : 2;
+  const int long_heads = rlx ? 2 : J0 >= 32 ? 32 : J0 >= 16 ? 24 : 2;
   P->chunk = d->chunk ? d->chunk : (!rlx && J0 >= 32 ? 1024 : 512);
   // an explicit head, the relaxed default, or 0: each mode picks its own up to head_cap
   P->head = d->head ? d->head : rlx ? 2 * P->chunk : 0;

@@ -247,37 +247,59 @@ def test_refuses_dims_beyond_32bit_gather_offsets():
     assert ok.mode_info(0)["rows"] == lim - 1
 
 
+def _default_head(lens, chunk, J, shares_g):
+    """The plan's default head of one mode, restated: the longest of 2..32 chunks (the listed counts), up to
+    the cap (32 chunks at J >= 32, 24 at J = 16), not above L_q (the row length reached by the longest rows
+    holding a quarter of the elements) and passing r_a h <= 0.8 (r_s S(h) + M(h))."""
+    lens = np.sort(lens[lens > 0])[::-1].astype(np.int64)
+    cs = np.cumsum(lens)
+    lq = int(lens[min(np.searchsorted(4 * cs, cs[-1]), len(lens) - 1)])
+    cap = chunk * (32 if J >= 32 else 24 if J >= 16 else 2)
+    ra = (1200.0 if shares_g else 2358.0) if J >= 32 else (2000.0 if shares_g else 3100.0)
+    rs = ((0.2 if J >= 32 else 0.3) if shares_g else 0.5)
+    h = 2 * chunk
+    for k in (3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32):
+        c = k * chunk
+        if c > cap or c > lq:
+            break
+        S = float(np.minimum(lens, c).sum())
+        M = float(np.maximum(lens - c, 0).sum())
+        if ra * min(c, int(lens[0])) > 0.8 * (rs * S + M):
+            break
+        h = c
+    return h
+
+
 def test_default_head_per_mode():
-    """Exact plans pick each mode's head: the largest chunk * 2^k from two chunks up to the cap (16 chunks of
-    1024 at J = 32 and order 3) not above the row length reached by the longest rows holding a quarter of
-    the mode's elements; an explicit head and relaxed plans (two chunks) are kept as given."""
-    dims, J, R = [40, 50, 2], 32, 32
-    c = np.stack(np.meshgrid(np.arange(40), np.arange(50), np.arange(2), indexing="ij")).reshape(3, -1)
-    c = np.repeat(c, 1, axis=1).astype(np.int32)
-    # every cell once: rows of 100 (mode 0), 80 (mode 1) and 2000 elements (mode 2)
-    v = np.ones(c.shape[1], dtype=np.float32)
-
-    def q25(m):
-        L = np.sort(np.bincount(c[m], minlength=dims[m]))[::-1]
-        cs = np.cumsum(L)
-        return int(L[np.searchsorted(cs, cs[-1] / 4)])
-
-    def rule(lq, chunk, cap):
-        h = 2 * chunk
-        while 2 * h <= lq and 2 * h <= cap:
-            h *= 2
-        return h
-
-    for chunk in (16, 64):
-        plan = _plan(dims, J, R, c, v, chunk=chunk)
+    """Exact plans pick each mode's head from its row lengths: the L_q bound binds on many rows of similar
+    length, the chain bound on a few long rows, the cap on long Zipf rows; an explicit head and relaxed plans
+    (two chunks) are kept as given."""
+    J = R = 32
+    # mode 0: 20 rows of about 20000 (chain bound); modes 1, 2: 2000 rows of about 200 (L_q bound)
+    dims = [20, 2000, 2000]
+    c, _ = synth.coords(dims, 400_000, 0.0, seed=11)
+    v = synth.values(c.shape[1], "int1to5", seed=11)
+    chunk = 16
+    plan = _plan(dims, J, R, c, v, chunk=chunk)
+    heads = []
+    for m in range(3):
+        info = plan.mode_info(m)
+        lens = np.bincount(c[m], minlength=dims[m])
+        assert info["chunk"] == chunk
+        want = _default_head(lens, chunk, J, bool(info["fiber_shared"]))
+        assert info["head"] == want, (m, info["head"], want)
+        heads.append(info["head"])
+    assert heads[0] < 20000 // 2 and heads[1] <= 200
+    # Zipf rows, most elements in long rows: the cap (32 chunks at J = 32, 24 at J = 16) in modes 1 and 2
+    dz = [20000, 50, 20]
+    cz, _ = synth.coords(dz, 2_000_000, 1.3, seed=3)
+    vz = synth.values(cz.shape[1], "int1to5", seed=3)
+    for Jz, cap in ((32, 32), (16, 24)):
+        pz = _plan(dz, Jz, Jz, cz, vz, chunk=16)
         for m in range(3):
-            info = plan.mode_info(m)
-            assert info["chunk"] == chunk
-            assert info["head"] == rule(q25(m), chunk, 16 * chunk), (chunk, m, info["head"], q25(m))
+            info = pz.mode_info(m)
+            lens = np.bincount(cz[m], minlength=dz[m])
+            assert info["head"] == _default_head(lens, 16, Jz, bool(info["fiber_shared"])), (Jz, m, info["head"])
+        assert [pz.mode_info(m)["head"] for m in (1, 2)] == [cap * 16] * 2
     assert [_plan(dims, J, R, c, v, chunk=16, head=48).mode_info(m)["head"] for m in range(3)] == [48] * 3
     assert [_plan(dims, J, R, c, v, chunk=16, relaxed=True).mode_info(m)["head"] for m in range(3)] == [32] * 3
-    # a Zipf mode whose long rows hold most elements takes the cap
-    cz, _ = synth.coords([4000, 30, 20], 60000, 1.3, seed=3)
-    vz = synth.values(60000, "int1to5", seed=3)
-    pz = _plan([4000, 30, 20], J, R, cz, vz, chunk=16)
-    assert pz.mode_info(2)["head"] == 16 * 16
