@@ -309,7 +309,7 @@ def rooflines(w, nnz, c, plan, prof, steps, storage, relaxed, counters_ok):
         if k in ("segsum", "loss"):
             # the bytes against HBM are the stream; the gathered C rows come through the caches, and
             # the CU's vector-memory data path is what saturates (rocprofv3 TD/TA busy counters)
-            r["limiter"] = ("vector-memory data path of the CUs (TD 93-96 % busy, TA 85-91 %), "
+            r["limiter"] = ("vector-memory data path of the CUs (TD 92-95 % busy, TA 84-90 %), "
                             "profiles/netflix32_fp32_segment_pass_limiter.md")
         return r
 
