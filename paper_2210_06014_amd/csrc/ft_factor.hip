@@ -487,9 +487,14 @@ __global__ __launch_bounds__(256) void k_combine(const CItem* __restrict__ items
                                                  double* __restrict__ map_scale) {
   constexpr int MS = J * J + J;
   constexpr int F = combine_fanin<J>();
-  constexpr int RMAX = (F / 2 * J * J + 255) / 256;  // matrix entries per thread at the widest level
-  constexpr int VMAX = (F / 2 * J + 255) / 256;      // vector entries per thread at the widest level
-  __shared__ float buf[F * MS];
+  // J >= 32: a thread forms a 4 x 4 tile of a product (T = 4); below, one
+  // entry (T = 1), which keeps all 256 threads busy on the smaller maps
+  constexpr int T = J >= 32 ? 4 : 1;
+  constexpr int T4 = J / T;                            // output tiles per side of a product
+  constexpr int TMAX = (F / 2 * T4 * T4 + 255) / 256;  // output tiles per thread at the widest level
+  constexpr int VMAX = (F / 2 * J + 255) / 256;        // vector entries per thread at the widest level
+  static_assert(J % 4 == 0 && MS % 4 == 0, "16-byte LDS reads of map columns");
+  __shared__ __align__(16) float buf[F * MS];
   __shared__ double sc[F];
   const CItem it = items[blockIdx.x];
   const int t = threadIdx.x;
@@ -502,19 +507,53 @@ __global__ __launch_bounds__(256) void k_combine(const CItem* __restrict__ items
   __syncthreads();
   for (int stride = 1; stride < count; stride *= 2) {
     const int pairs = (count - stride + 2 * stride - 1) / (2 * stride);  // a = 2 k stride, b = a + stride < count
-    float res[RMAX];
+    // (N_b N_a)(i, j) = sum_q N_b(i, q) N_a(q, j), q in order, for a T x T
+    // tile of (i, j) per thread.  Columns are contiguous (entry (i, j) at
+    // j J + i), so with T = 4 each step of four q reads four columns of N_a
+    // and four of N_b with 16-byte loads for 64 FMAs.
+    float res[TMAX][T][T];
 #pragma unroll
-    for (int u = 0; u < RMAX; ++u) {
+    for (int u = 0; u < TMAX; ++u) {
       const int e = t + 256 * u;
-      if (e < pairs * J * J) {
-        const int pr = e / (J * J), ij = e % (J * J);
-        const int i = ij % J, j = ij / J;
+      if (e < pairs * T4 * T4) {
+        const int pr = e / (T4 * T4), rem = e % (T4 * T4);
+        const int i0 = T * (rem % T4), j0 = T * (rem / T4);
         const float* Na = buf + (2 * pr * stride) * MS;
         const float* Nb = Na + stride * MS;
-        float acc = 0.f;
+        if constexpr (T == 1) {
+          float acc = 0.f;
 #pragma unroll
-        for (int q = 0; q < J; ++q) acc = fmaf(Nb[q * J + i], Na[j * J + q], acc);
-        res[u] = (Na[ij] + Nb[ij]) + acc;
+          for (int q = 0; q < J; ++q) acc = fmaf(Nb[q * J + i0], Na[j0 * J + q], acc);
+          const int ij = j0 * J + i0;
+          res[u][0][0] = (Na[ij] + Nb[ij]) + acc;
+        } else {
+          float acc[4][4];  // acc[c][r]: entry (i0 + r, j0 + c)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[c][r] = 0.f;
+#pragma unroll
+          for (int q0 = 0; q0 < J; q0 += 4) {
+            floatx4 na[4], nb[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) na[c] = *reinterpret_cast<const floatx4*>(Na + (j0 + c) * J + q0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) nb[k] = *reinterpret_cast<const floatx4*>(Nb + (q0 + k) * J + i0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+              for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[c][r] = fmaf(nb[k][r], na[c][k], acc[c][r]);
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int ij = (j0 + c) * J + i0 + r;
+              res[u][c][r] = (Na[ij] + Nb[ij]) + acc[c][r];
+            }
+        }
       }
     }
     float vres[VMAX];
@@ -536,11 +575,15 @@ __global__ __launch_bounds__(256) void k_combine(const CItem* __restrict__ items
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < RMAX; ++u) {
+    for (int u = 0; u < TMAX; ++u) {
       const int e = t + 256 * u;
-      if (e < pairs * J * J) {
-        const int pr = e / (J * J), ij = e % (J * J);
-        buf[(2 * pr * stride) * MS + ij] = res[u];
+      if (e < pairs * T4 * T4) {
+        const int pr = e / (T4 * T4), rem = e % (T4 * T4);
+        const int i0 = T * (rem % T4), j0 = T * (rem / T4);
+#pragma unroll
+        for (int c = 0; c < T; ++c)
+#pragma unroll
+          for (int r = 0; r < T; ++r) buf[(2 * pr * stride) * MS + (j0 + c) * J + i0 + r] = res[u][c][r];
       }
     }
 #pragma unroll
