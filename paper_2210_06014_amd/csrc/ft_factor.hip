@@ -4,6 +4,8 @@
 namespace ft {
 namespace {
 
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+
 // ---------------------------------------------------------------------------
 // Factor pass.  Each element x of a row, in order:
 //     w = prod_{n != m} C(n)[i_n, :],  g = B(m) w,  e = x - a.g,
@@ -487,9 +489,9 @@ __global__ __launch_bounds__(256) void k_combine(const CItem* __restrict__ items
                                                  double* __restrict__ map_scale) {
   constexpr int MS = J * J + J;
   constexpr int F = combine_fanin<J>();
-  // J >= 32: a thread forms a 4 x 4 tile of a product (T = 4); below, one
-  // entry (T = 1), which keeps all 256 threads busy on the smaller maps
-  constexpr int T = J >= 32 ? 4 : 1;
+  // a thread forms a T x T tile of a product: 4 x 4 at J = 32, 2 x 2 at
+  // J = 16 (fan-in 16: 512 tiles for the 256 threads), one entry at J = 8
+  constexpr int T = J >= 32 ? 4 : J >= 16 ? 2 : 1;
   constexpr int T4 = J / T;                            // output tiles per side of a product
   constexpr int TMAX = (F / 2 * T4 * T4 + 255) / 256;  // output tiles per thread at the widest level
   constexpr int VMAX = (F / 2 * J + 255) / 256;        // vector entries per thread at the widest level
@@ -509,8 +511,8 @@ __global__ __launch_bounds__(256) void k_combine(const CItem* __restrict__ items
     const int pairs = (count - stride + 2 * stride - 1) / (2 * stride);  // a = 2 k stride, b = a + stride < count
     // (N_b N_a)(i, j) = sum_q N_b(i, q) N_a(q, j), q in order, for a T x T
     // tile of (i, j) per thread.  Columns are contiguous (entry (i, j) at
-    // j J + i), so with T = 4 each step of four q reads four columns of N_a
-    // and four of N_b with 16-byte loads for 64 FMAs.
+    // j J + i), so each step of four q reads T columns of N_a (16 bytes
+    // each) and four column pieces of N_b (4 T bytes each) for 4 T^2 FMAs.
     float res[TMAX][T][T];
 #pragma unroll
     for (int u = 0; u < TMAX; ++u) {
@@ -527,29 +529,31 @@ __global__ __launch_bounds__(256) void k_combine(const CItem* __restrict__ items
           const int ij = j0 * J + i0;
           res[u][0][0] = (Na[ij] + Nb[ij]) + acc;
         } else {
-          float acc[4][4];  // acc[c][r]: entry (i0 + r, j0 + c)
+          using Vec = typename std::conditional<T == 4, floatx4, floatx2>::type;
+          float acc[T][T];  // acc[c][r]: entry (i0 + r, j0 + c)
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
+          for (int c = 0; c < T; ++c)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[c][r] = 0.f;
+            for (int r = 0; r < T; ++r) acc[c][r] = 0.f;
 #pragma unroll
           for (int q0 = 0; q0 < J; q0 += 4) {
-            floatx4 na[4], nb[4];
+            floatx4 na[T];
+            Vec nb[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) na[c] = *reinterpret_cast<const floatx4*>(Na + (j0 + c) * J + q0);
+            for (int c = 0; c < T; ++c) na[c] = *reinterpret_cast<const floatx4*>(Na + (j0 + c) * J + q0);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) nb[k] = *reinterpret_cast<const floatx4*>(Nb + (q0 + k) * J + i0);
+            for (int k = 0; k < 4; ++k) nb[k] = *reinterpret_cast<const Vec*>(Nb + (q0 + k) * J + i0);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
 #pragma unroll
-              for (int c = 0; c < 4; ++c)
+              for (int c = 0; c < T; ++c)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[c][r] = fmaf(nb[k][r], na[c][k], acc[c][r]);
+                for (int r = 0; r < T; ++r) acc[c][r] = fmaf(nb[k][r], na[c][k], acc[c][r]);
           }
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
+          for (int c = 0; c < T; ++c)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int r = 0; r < T; ++r) {
               const int ij = (j0 + c) * J + i0 + r;
               res[u][c][r] = (Na[ij] + Nb[ij]) + acc[c][r];
             }
